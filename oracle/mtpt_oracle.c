@@ -1,0 +1,653 @@
+/*
+ * mtpt_oracle.c -- TEST INFRASTRUCTURE, NOT PART OF THE PRODUCT.
+ *
+ * A plain, slow, obviously correct FP64 CPU implementation of one time step of
+ * mass-transfer particle tracking (MTPT), following Schauer et al.,
+ * "Parallelized domain decomposition for mass transfer particle tracking
+ * simulations" (arXiv 2204.03756), Sec. 3.  It exists only to check the HIP
+ * path: only the tests, the smoke check and the benchmark's CPU-baseline leg
+ * load it.  It shares no source, header, table or helper with the HIP path.
+ *
+ * Build: gcc -O2 -ffp-contract=off -fopenmp -fPIC -shared (see build.py).
+ * Contraction is off so that every "+", "-", "*" below is one IEEE operation.
+ *
+ * Layouts (all in original particle order, "pid" = index):
+ *   positions  x[n][dim]   double (row-major)
+ *   masses     m[S][n]     double (species-major)
+ *   neighbours CSR row_ptr[n+1], col[nnz] int64, each row sorted ascending,
+ *              the particle itself included.
+ *
+ * Functions and the passage each follows:
+ *   or_philox4x32_10     Philox4x32-10 (Salmon et al., SC'11); the paper only
+ *                        asks for standard-normal jumps (Sec. 3).
+ *   or_log, or_sincos_2pi, or_normals
+ *                        Box-Muller from two Philox uniforms, with log, sin and
+ *                        cos evaluated from their series (no libm), so that any
+ *                        other implementation of the same recipe can agree bit
+ *                        for bit.
+ *   or_rw_step           Sec. 3: random-walk update X += xi*sqrt(2 D_RW dt) and
+ *                        zero-flux walls as elastic reflection.
+ *   or_neighbors         Sec. 3: neighbours within the search radius psi,
+ *                        Eq. (1); K-D tree range search (Bentley) or brute force.
+ *   or_mt_weights        Sec. 3: Gaussian kernel Eq. (2)/(3) without its
+ *                        prefactor (it cancels), and the symmetric normalisation
+ *                        W_ij = K_ij / (0.5 (sum_k K_ik + sum_k K_kj)).
+ *   or_mt_step           Sec. 3, Eq. (4) and Eq. (5): M_i += sum_j beta (M_j - M_i) W_ij.
+ *   or_react             A+B->C mass-based reaction; not in the paper (named there
+ *                        as future work in Sec. 8): parity unpinned against the
+ *                        paper, pinned only by invariants and a closed form.
+ *   or_total             Neumaier-compensated FP64 sum of a mass array.
+ *   or_run               the whole step loop.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* ------------------------------------------------------------------ */
+/* Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11, "Parallel random   */
+/* numbers: as easy as 1, 2, 3").  Round function: two 32x32->64       */
+/* multiplies by fixed multipliers, the high halves xored with the     */
+/* other two words and the round key, words permuted; the key is       */
+/* bumped by the Weyl constants between rounds.                         */
+/* ------------------------------------------------------------------ */
+void or_philox4x32_10(const uint32_t ctr_in[4], const uint32_t key_in[2], uint32_t out[4])
+{
+    uint32_t c0 = ctr_in[0], c1 = ctr_in[1], c2 = ctr_in[2], c3 = ctr_in[3];
+    uint32_t k0 = key_in[0], k1 = key_in[1];
+    for (int round = 0; round < 10; ++round) {
+        if (round > 0) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)c0;
+        uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
+        uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        uint32_t n0 = hi1 ^ c1 ^ k0;
+        uint32_t n1 = lo1;
+        uint32_t n2 = hi0 ^ c3 ^ k1;
+        uint32_t n3 = lo0;
+        c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+/* Uniform in (0,1) from 52 random bits: u = (2k+1) 2^-53, exact in FP64,
+ * never 0 or 1.  k = high word (32 bits) then the top 20 bits of the low word. */
+double or_uniform52(uint32_t lo_word, uint32_t hi_word)
+{
+    uint64_t k = ((uint64_t)hi_word << 20) | (uint64_t)(lo_word >> 12);
+    return (double)(2u * k + 1u) * 0x1p-53;
+}
+
+/* Natural log of u in (0,1), from u = m 2^e with m in [sqrt(1/2), sqrt(2)]:
+ *   log m = 2 atanh(s) = 2 (s + s^3/3 + s^5/5 + ...),  s = (m-1)/(m+1),
+ * |s| <= 0.1716, truncated after s^23 (remainder < 1e-19 relative);
+ *   log u = e ln2 + log m, with ln2 split into a 42-bit head (exact products)
+ * and a tail. */
+static const double OR_LN2_HI = 0.6931471805598903;      /* 0x1.62e42fefa38p-1 */
+static const double OR_LN2_LO = 5.497923018708371e-14;   /* ln2 - OR_LN2_HI   */
+static const double OR_SQRT2 = 1.4142135623730951;
+
+double or_log(double u)
+{
+    uint64_t bits;
+    memcpy(&bits, &u, sizeof bits);
+    int e = (int)((bits >> 52) & 0x7ffu) - 1023;
+    uint64_t mbits = (bits & 0x000fffffffffffffull) | 0x3ff0000000000000ull;
+    double m;
+    memcpy(&m, &mbits, sizeof m);
+    if (m > OR_SQRT2) {
+        m = m * 0.5;
+        e = e + 1;
+    }
+    double f = m - 1.0;
+    double s = f / (2.0 + f);
+    double z = s * s;
+    /* t = 1/3 + z (1/5 + z (1/7 + ... + z (1/23))) */
+    double t = 1.0 / 23.0;
+    for (int k = 10; k >= 1; --k)
+        t = 1.0 / (double)(2 * k + 1) + z * t;
+    double ts = s + s;
+    double lm = ts + ts * (z * t);
+    double r = (double)e * OR_LN2_LO;
+    r = r + lm;
+    return (double)e * OR_LN2_HI + r;
+}
+
+/* sin and cos of 2 pi u for u in (0,1).  4u = q + f (exact), q the quadrant;
+ * the angle inside the quadrant is f pi/2, folded to y in [0, pi/4] by
+ * sin(pi/2 - y) = cos y.  On [0, pi/4] the Taylor series are nested:
+ *   sin y = y (1 - z/(2.3) (1 - z/(4.5) (1 - ... (1 - z/(18.19))))),
+ *   cos y =    1 - z/(1.2) (1 - z/(3.4) (1 - ... (1 - z/(17.18)))),  z = y^2.  */
+static const double OR_HALF_PI = 1.5707963267948966;
+
+void or_sincos_2pi(double u, double* s_out, double* c_out)
+{
+    double v = 4.0 * u;
+    int q = (int)v;
+    double f = v - (double)q;
+    double y;
+    int swap;
+    if (f <= 0.5) {
+        y = f * OR_HALF_PI;
+        swap = 0;
+    } else {
+        y = (1.0 - f) * OR_HALF_PI;
+        swap = 1;
+    }
+    double z = y * y;
+    double ts = 1.0, tc = 1.0;
+    for (int k = 9; k >= 1; --k) {
+        double rs = 1.0 / (double)((2 * k) * (2 * k + 1));
+        double rc = 1.0 / (double)((2 * k - 1) * (2 * k));
+        ts = 1.0 - (z * rs) * ts;
+        tc = 1.0 - (z * rc) * tc;
+    }
+    double sy = y * ts, cy = tc;
+    double sp = swap ? cy : sy; /* sin of the in-quadrant angle */
+    double cp = swap ? sy : cy; /* cos of the in-quadrant angle */
+    double s, c;
+    switch (q & 3) {
+    case 0: s = sp;  c = cp;  break;
+    case 1: s = cp;  c = -sp; break;
+    case 2: s = -sp; c = -cp; break;
+    default: s = -cp; c = sp; break;
+    }
+    *s_out = s;
+    *c_out = c;
+}
+
+/* Two standard normals by Box-Muller from one Philox call.
+ * key = (seed low word, seed high word); counter = (pid, call, step low word,
+ * step high word).  u1 from words 0,1 and u2 from words 2,3;
+ * z0 = sqrt(-2 log u1) cos(2 pi u2), z1 = sqrt(-2 log u1) sin(2 pi u2). */
+void or_normal_pair(uint64_t seed, int64_t step, uint32_t pid, uint32_t call, double z[2])
+{
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    uint32_t ctr[4] = {pid, call, (uint32_t)(uint64_t)step, (uint32_t)((uint64_t)step >> 32)};
+    uint32_t w[4];
+    or_philox4x32_10(ctr, key, w);
+    double u1 = or_uniform52(w[0], w[1]);
+    double u2 = or_uniform52(w[2], w[3]);
+    double r = sqrt(-2.0 * or_log(u1));
+    double sn, cs;
+    or_sincos_2pi(u2, &sn, &cs);
+    z[0] = r * cs;
+    z[1] = r * sn;
+}
+
+/* The d standard-normal components of particle pid's jump at a step: call 0
+ * gives dimensions 0 and 1, call 1 gives dimension 2 (its z0). */
+void or_normals(uint64_t seed, int64_t step, int dim, int64_t n, double* xi /* [n][dim] */)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t p = 0; p < n; ++p) {
+        double z[2];
+        or_normal_pair(seed, step, (uint32_t)p, 0u, z);
+        xi[p * dim + 0] = z[0];
+        xi[p * dim + 1] = z[1];
+        if (dim == 3) {
+            or_normal_pair(seed, step, (uint32_t)p, 1u, z);
+            xi[p * dim + 2] = z[0];
+        }
+    }
+}
+
+/* ------------------------------------------------------------------ */
+/* Sec. 3: random walk X_i(t+dt) = X_i(t) + xi_i sqrt(2 D_RW dt), then  */
+/* zero-flux walls as elastic reflection: a coordinate that left the    */
+/* box is mirrored about the wall it crossed, repeatedly until inside.  */
+/* fp32 != 0: the position state is FP32 (inputs already rounded); the  */
+/* jump is formed in FP64 and rounded once, the add and the reflection  */
+/* are done in float.                                                    */
+/* ------------------------------------------------------------------ */
+void or_rw_step(int dim, int64_t n, const double lo[3], const double hi[3], double d_rw,
+                double dt, uint64_t seed, int64_t step, int fp32, double* x /* [n][dim] */)
+{
+    double sdev = sqrt(2.0 * d_rw * dt);
+#pragma omp parallel for schedule(static)
+    for (int64_t p = 0; p < n; ++p) {
+        double z[3], zz[2];
+        or_normal_pair(seed, step, (uint32_t)p, 0u, zz);
+        z[0] = zz[0];
+        z[1] = zz[1];
+        if (dim == 3) {
+            or_normal_pair(seed, step, (uint32_t)p, 1u, zz);
+            z[2] = zz[0];
+        }
+        for (int k = 0; k < dim; ++k) {
+            double jump = z[k] * sdev;
+            if (fp32) {
+                float xf = (float)x[p * dim + k];
+                float jf = (float)jump;
+                float lf = (float)lo[k], hf = (float)hi[k];
+                xf = xf + jf;
+                while (xf < lf || xf > hf)
+                    xf = (xf < lf) ? 2.0f * lf - xf : 2.0f * hf - xf;
+                x[p * dim + k] = (double)xf;
+            } else {
+                double xd = x[p * dim + k] + jump;
+                while (xd < lo[k] || xd > hi[k])
+                    xd = (xd < lo[k]) ? 2.0 * lo[k] - xd : 2.0 * hi[k] - xd;
+                x[p * dim + k] = xd;
+            }
+        }
+    }
+}
+
+/* ------------------------------------------------------------------ */
+/* Squared distance, one fixed operation order for every caller:        */
+/* ((dx0*dx0) + (dx1*dx1)) + (dx2*dx2), dx = x_j - x_i.                 */
+/* ------------------------------------------------------------------ */
+static double or_r2(int dim, const double* xi, const double* xj)
+{
+    double d0 = xj[0] - xi[0];
+    double d1 = xj[1] - xi[1];
+    double r2 = d0 * d0 + d1 * d1;
+    if (dim == 3) {
+        double d2 = xj[2] - xi[2];
+        r2 = r2 + d2 * d2;
+    }
+    return r2;
+}
+
+/* ------------------------------------------------------------------ */
+/* K-D tree (Bentley 1975), as used by the paper for the range search   */
+/* within psi (Sec. 3).  Median split cycling through the dimensions,   */
+/* leaves of at most OR_LEAF points.                                     */
+/* ------------------------------------------------------------------ */
+#define OR_LEAF 12
+
+typedef struct {
+    int dim;
+    const double* x;
+    int64_t* idx;    /* permutation of 0..n-1, reordered by the build */
+    double* split;   /* splitting value per inner node, heap-numbered (root 1) */
+} or_tree;
+
+static double or_coord(const or_tree* t, int64_t k, int ax) { return t->x[t->idx[k] * t->dim + ax]; }
+
+static void or_swap(int64_t* a, int64_t* b)
+{
+    int64_t tmp = *a;
+    *a = *b;
+    *b = tmp;
+}
+
+/* Quickselect: reorder idx[lo..hi) so that position k holds the element of
+ * rank k-lo along axis ax, smaller-or-equal ones before it and
+ * greater-or-equal ones after it. */
+static void or_select(or_tree* t, int64_t lo, int64_t hi, int64_t k, int ax)
+{
+    while (hi - lo > 1) {
+        int64_t mid = lo + (hi - lo) / 2;
+        /* median of three as pivot */
+        double a = or_coord(t, lo, ax), b = or_coord(t, mid, ax), c = or_coord(t, hi - 1, ax);
+        int64_t piv = (a < b) ? ((b < c) ? mid : ((a < c) ? hi - 1 : lo))
+                              : ((a < c) ? lo : ((b < c) ? hi - 1 : mid));
+        double pv = or_coord(t, piv, ax);
+        or_swap(&t->idx[piv], &t->idx[hi - 1]);
+        int64_t store = lo;
+        for (int64_t i = lo; i < hi - 1; ++i) {
+            if (or_coord(t, i, ax) < pv) {
+                or_swap(&t->idx[i], &t->idx[store]);
+                ++store;
+            }
+        }
+        or_swap(&t->idx[store], &t->idx[hi - 1]);
+        if (store == k)
+            return;
+        if (k < store)
+            hi = store;
+        else
+            lo = store + 1;
+    }
+}
+
+/* The splitting value is recorded before the children are built, because
+ * building the right child reorders the slot the median sits in. */
+static void or_build(or_tree* t, int64_t node, int64_t lo, int64_t hi, int depth)
+{
+    if (hi - lo <= OR_LEAF)
+        return;
+    int ax = depth % t->dim;
+    int64_t mid = lo + (hi - lo) / 2;
+    or_select(t, lo, hi, mid, ax);
+    t->split[node] = or_coord(t, mid, ax);
+    or_build(t, 2 * node, lo, mid, depth + 1);
+    or_build(t, 2 * node + 1, mid, hi, depth + 1);
+}
+
+/* Number of heap slots the build can touch: sizes at depth d are at most
+ * ceil(n / 2^d), and a node of at most OR_LEAF points is a leaf. */
+static int64_t or_tree_slots(int64_t n)
+{
+    int64_t slots = 2, size = n;
+    while (size > OR_LEAF) {
+        size = (size + 1) / 2;
+        slots *= 2;
+    }
+    return slots;
+}
+
+/* Range query: every point p with r2(q, p) <= psi2.  A subtree is skipped
+ * only when the squared distance to its splitting plane, computed in FP64,
+ * already exceeds psi2: by monotone rounding the computed r2 of every point
+ * beyond the plane is then larger too, so no pair the brute-force search
+ * accepts is lost. */
+static void or_query(const or_tree* t, int64_t node, int64_t lo, int64_t hi, int depth,
+                     const double* q, double psi2, int64_t* out, int64_t* count, int64_t cap)
+{
+    if (hi - lo <= OR_LEAF) {
+        for (int64_t k = lo; k < hi; ++k) {
+            int64_t j = t->idx[k];
+            if (or_r2(t->dim, q, t->x + j * t->dim) <= psi2) {
+                if (*count < cap)
+                    out[*count] = j;
+                ++*count;
+            }
+        }
+        return;
+    }
+    int ax = depth % t->dim;
+    int64_t mid = lo + (hi - lo) / 2;
+    double split = t->split[node];
+    double diff = split - q[ax];
+    if (q[ax] < split) {
+        or_query(t, 2 * node, lo, mid, depth + 1, q, psi2, out, count, cap);
+        if (diff * diff <= psi2)
+            or_query(t, 2 * node + 1, mid, hi, depth + 1, q, psi2, out, count, cap);
+    } else {
+        or_query(t, 2 * node + 1, mid, hi, depth + 1, q, psi2, out, count, cap);
+        if (diff * diff <= psi2)
+            or_query(t, 2 * node, lo, mid, depth + 1, q, psi2, out, count, cap);
+    }
+}
+
+static int or_cmp_i64(const void* a, const void* b)
+{
+    int64_t x = *(const int64_t*)a, y = *(const int64_t*)b;
+    return (x > y) - (x < y);
+}
+
+/* Neighbour sets N(i) = { j : r2_ij <= psi2 }, i included (Sec. 3).
+ * method 0: brute force over all pairs; method 1: K-D tree.
+ * Writes row_ptr[n+1] always; writes col only if the total fits in cap.
+ * Returns nnz, or -1 on allocation failure. */
+int64_t or_neighbors(int dim, int64_t n, const double* x, double psi2, int method, int64_t* row_ptr,
+                     int64_t* col, int64_t cap)
+{
+    or_tree tree = {dim, x, NULL, NULL};
+    if (method == 1) {
+        tree.idx = (int64_t*)malloc((size_t)(n > 0 ? n : 1) * sizeof(int64_t));
+        tree.split = (double*)malloc((size_t)or_tree_slots(n) * sizeof(double));
+        if (!tree.idx || !tree.split) {
+            free(tree.idx);
+            free(tree.split);
+            return -1;
+        }
+        for (int64_t i = 0; i < n; ++i)
+            tree.idx[i] = i;
+        or_build(&tree, 1, 0, n, 0);
+    }
+    int64_t* cnt = (int64_t*)calloc((size_t)(n > 0 ? n : 1), sizeof(int64_t));
+    if (!cnt) {
+        free(tree.idx);
+        free(tree.split);
+        return -1;
+    }
+    /* pass 1: counts */
+#pragma omp parallel for schedule(dynamic, 1024)
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t c = 0;
+        if (method == 1) {
+            or_query(&tree, 1, 0, n, 0, x + i * dim, psi2, NULL, &c, 0);
+        } else {
+            for (int64_t j = 0; j < n; ++j)
+                if (or_r2(dim, x + i * dim, x + j * dim) <= psi2)
+                    ++c;
+        }
+        cnt[i] = c;
+    }
+    row_ptr[0] = 0;
+    for (int64_t i = 0; i < n; ++i)
+        row_ptr[i + 1] = row_ptr[i] + cnt[i];
+    int64_t nnz = row_ptr[n];
+    if (col && nnz <= cap) {
+        /* pass 2: fill, then sort each row ascending */
+#pragma omp parallel for schedule(dynamic, 1024)
+        for (int64_t i = 0; i < n; ++i) {
+            int64_t* row = col + row_ptr[i];
+            int64_t c = 0;
+            if (method == 1) {
+                or_query(&tree, 1, 0, n, 0, x + i * dim, psi2, row, &c, cnt[i]);
+            } else {
+                for (int64_t j = 0; j < n; ++j)
+                    if (or_r2(dim, x + i * dim, x + j * dim) <= psi2)
+                        row[c++] = j;
+            }
+            qsort(row, (size_t)cnt[i], sizeof(int64_t), or_cmp_i64);
+        }
+    }
+    free(cnt);
+    free(tree.idx);
+    free(tree.split);
+    return nnz;
+}
+
+/* ------------------------------------------------------------------ */
+/* Sec. 3, Eq. (2)-(3): Gaussian mass-transfer kernel with the          */
+/* bandwidth set by beta, K_ij = exp(-beta r2 / (4 D_MT dt)); the       */
+/* normalising prefactor is dropped because it cancels in W.  Then the  */
+/* symmetric normalisation by the mean of the row and column sums,      */
+/* W_ij = K_ij / (0.5 (s_i + s_j)),  s_i = sum_{k in N(i)} K_ik,        */
+/* with the self term K_ii = 1 included (the sums run over all k).      */
+/* K and W are written per CSR entry; W_ii is written as 0 (it never    */
+/* moves mass).                                                          */
+/* ------------------------------------------------------------------ */
+void or_mt_weights(int dim, int64_t n, const double* x, double d_mt, double dt, double beta,
+                   const int64_t* row_ptr, const int64_t* col, double* s /* [n] */,
+                   double* kv /* [nnz] or NULL */, double* wv /* [nnz] or NULL */)
+{
+    double denom = 4.0 * d_mt * dt;
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+        double acc = 0.0;
+        for (int64_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e) {
+            int64_t j = col[e];
+            double r2 = or_r2(dim, x + i * dim, x + j * dim);
+            double k = exp(-(beta * r2) / denom);
+            if (kv)
+                kv[e] = k;
+            acc = acc + k;
+        }
+        s[i] = acc;
+    }
+    if (wv) {
+#pragma omp parallel for schedule(static)
+        for (int64_t i = 0; i < n; ++i) {
+            for (int64_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e) {
+                int64_t j = col[e];
+                if (j == i) {
+                    wv[e] = 0.0;
+                    continue;
+                }
+                double r2 = or_r2(dim, x + i * dim, x + j * dim);
+                double k = exp(-(beta * r2) / denom);
+                wv[e] = k / (0.5 * (s[i] + s[j]));
+            }
+        }
+    }
+}
+
+/* Sec. 3, Eq. (4)-(5): explicit update M_i(t+dt) = M_i(t) + delta_i with
+ * delta_i = sum_j beta (M_j(t) - M_i(t)) W_ij, every delta from M(t) (the
+ * right-hand side uses time t only), summed in ascending j.
+ * m_in and m_out are [S][n] and must not alias.  Returns the number of
+ * ordered pairs i != j within psi. */
+int64_t or_mt_step(int dim, int64_t n, int n_species, const double* x, const double* m_in,
+                   double* m_out, double d_mt, double dt, double beta, double psi, int method)
+{
+    double psi2 = psi * psi;
+    int64_t* row_ptr = (int64_t*)malloc((size_t)(n + 1) * sizeof(int64_t));
+    if (!row_ptr)
+        return -1;
+    int64_t nnz = or_neighbors(dim, n, x, psi2, method, row_ptr, NULL, 0);
+    int64_t* col = (int64_t*)malloc((size_t)(nnz > 0 ? nnz : 1) * sizeof(int64_t));
+    double* wv = (double*)malloc((size_t)(nnz > 0 ? nnz : 1) * sizeof(double));
+    double* s = (double*)malloc((size_t)(n > 0 ? n : 1) * sizeof(double));
+    if (!col || !wv || !s) {
+        free(row_ptr); free(col); free(wv); free(s);
+        return -1;
+    }
+    or_neighbors(dim, n, x, psi2, method, row_ptr, col, nnz);
+    or_mt_weights(dim, n, x, d_mt, dt, beta, row_ptr, col, s, NULL, wv);
+    for (int c = 0; c < n_species; ++c) {
+        const double* mi = m_in + (int64_t)c * n;
+        double* mo = m_out + (int64_t)c * n;
+#pragma omp parallel for schedule(static)
+        for (int64_t i = 0; i < n; ++i) {
+            double delta = 0.0;
+            for (int64_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e) {
+                int64_t j = col[e];
+                if (j == i)
+                    continue;
+                delta = delta + (mi[j] - mi[i]) * wv[e];
+            }
+            mo[i] = mi[i] + beta * delta;
+        }
+    }
+    free(row_ptr); free(col); free(wv); free(s);
+    return nnz - n;
+}
+
+/* ------------------------------------------------------------------ */
+/* A + B -> C, well-mixed second order over dt inside each particle,    */
+/* on concentrations c = N M / V (Sec. 3's mass-to-concentration map,   */
+/* V the box volume).  da/dt = db/dt = -k a b has the exact solution    */
+/* with D = a - b >= 0 (swap otherwise):                                 */
+/*   a' = a D / (D - b expm1(-k D dt))   (D > 0),  a' = a/(1 + k a dt)   */
+/*   (D = 0),  b' = a' - D,  c' = c + (a - a').                          */
+/* m is [3][n]: species A, B, C.                                         */
+/* ------------------------------------------------------------------ */
+void or_react(int64_t n, double* m, double k_react, double dt, double n_total, double volume)
+{
+    double to_c = n_total / volume;
+    double to_m = volume / n_total;
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+        double a = m[i] * to_c;
+        double b = m[n + i] * to_c;
+        int swapped = 0;
+        if (b > a) {
+            double tmp = a;
+            a = b;
+            b = tmp;
+            swapped = 1;
+        }
+        double d = a - b;
+        double a_new;
+        if (d > 0.0)
+            a_new = a * d / (d - b * expm1(-k_react * d * dt));
+        else
+            a_new = a / (1.0 + k_react * a * dt);
+        double b_new = a_new - d;
+        double reacted = a - a_new;
+        if (swapped) {
+            double tmp = a_new;
+            a_new = b_new;
+            b_new = tmp;
+        }
+        m[i] = a_new * to_m;
+        m[n + i] = b_new * to_m;
+        m[2 * n + i] = m[2 * n + i] + reacted * to_m;
+    }
+}
+
+/* Neumaier-compensated FP64 sum (Neumaier 1974). */
+double or_total(int64_t n, const double* v)
+{
+    double sum = 0.0, comp = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        double t = sum + v[i];
+        if (fabs(sum) >= fabs(v[i]))
+            comp = comp + ((sum - t) + v[i]);
+        else
+            comp = comp + ((v[i] - t) + sum);
+        sum = t;
+    }
+    return sum + comp;
+}
+
+/* ------------------------------------------------------------------ */
+/* The step loop: for each step t = start_step .. start_step+steps-1,   */
+/*   random walk (if d_rw > 0) -> neighbours within psi -> weights ->   */
+/*   mass transfer -> reaction (3 species, k_react > 0) -> record.       */
+/* fp32 != 0 keeps the position state in FP32 (the caller passes        */
+/* positions already rounded to float); the mass transfer itself is     */
+/* always FP64.  pairs_out[steps] gets the ordered pairs i != j per step */
+/* and totals_out[steps][S] the compensated mass totals after the step. */
+/* Returns 0, or -1 on allocation failure.                              */
+/* ------------------------------------------------------------------ */
+int or_run(int dim, int64_t n, int n_species, const double* lo, const double* hi, double d_rw,
+           double d_mt, double dt, double beta, double psi, double k_react, uint64_t seed,
+           int64_t start_step, int fp32, int method, int64_t steps, double* x, double* m,
+           int64_t* pairs_out, double* totals_out, int n_threads)
+{
+#ifdef _OPENMP
+    if (n_threads > 0)
+        omp_set_num_threads(n_threads);
+#else
+    (void)n_threads;
+#endif
+    double* m2 = (double*)malloc((size_t)n_species * (size_t)(n > 0 ? n : 1) * sizeof(double));
+    if (!m2)
+        return -1;
+    double volume = 1.0;
+    for (int k = 0; k < dim; ++k)
+        volume = volume * (hi[k] - lo[k]);
+    for (int64_t s = 0; s < steps; ++s) {
+        int64_t t = start_step + s;
+        if (d_rw > 0.0)
+            or_rw_step(dim, n, lo, hi, d_rw, dt, seed, t, fp32, x);
+        int64_t pairs = or_mt_step(dim, n, n_species, x, m, m2, d_mt, dt, beta, psi, method);
+        if (pairs < 0) {
+            free(m2);
+            return -1;
+        }
+        memcpy(m, m2, (size_t)n_species * (size_t)n * sizeof(double));
+        if (n_species == 3 && k_react > 0.0)
+            or_react(n, m, k_react, dt, (double)n, volume);
+        if (pairs_out)
+            pairs_out[s] = pairs;
+        if (totals_out)
+            for (int c = 0; c < n_species; ++c)
+                totals_out[s * n_species + c] = or_total(n, m + (int64_t)c * n);
+    }
+    free(m2);
+    return 0;
+}
+
+int or_max_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+void or_set_threads(int n_threads)
+{
+#ifdef _OPENMP
+    if (n_threads > 0)
+        omp_set_num_threads(n_threads);
+#else
+    (void)n_threads;
+#endif
+}
