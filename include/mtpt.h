@@ -1,0 +1,193 @@
+/*
+ * mtpt.h -- C-ABI of libmtpt.so: the per-time-step hot path of mass-transfer
+ * particle tracking (MTPT) on one AMD Instinct MI355X (gfx950).
+ *
+ * The method (Schauer et al., arXiv 2204.03756, Sec. 3):
+ *   1. random walk X_i += xi_i sqrt(2 D_RW dt), xi_i standard normal, with
+ *      zero-flux walls as elastic reflection;
+ *   2. neighbours within the search radius psi (Eq. (1));
+ *   3. Gaussian weights K_ij = exp(-beta r_ij^2 / (4 D_MT dt)) (Eq. (2)-(3),
+ *      the normalising prefactor cancels) and the symmetric normalisation
+ *      W_ij = K_ij / (0.5 (s_i + s_j)), s_i = sum_k K_ik (self term included);
+ *   4. explicit mass exchange M_i += beta sum_j W_ij (M_j - M_i) (Eq. (4)-(5)),
+ *      every increment computed from the masses at time t.
+ * An optional A+B->C reaction (three species) runs after the exchange.
+ *
+ * General rules for every function below:
+ *   - Return MTPT_OK (0) or a negative MTPT_E_* code; mtpt_last_error() then
+ *     holds a message (thread-local, valid until the next call on the thread).
+ *   - Host pointers are plain host memory owned by the caller; the library
+ *     copies inputs before returning and never keeps a host pointer.
+ *   - All device memory is owned by the library and taken from the allocator
+ *     passed at create (hipMalloc/hipFree when NULL).
+ *   - Work is enqueued on the stream given at create (a new stream of default
+ *     priority when NULL).  Only the functions marked "synchronises" wait.
+ *   - A handle is not thread-safe; distinct handles are independent.
+ *   - Positions are exchanged as FP64 [n][dim], masses as FP64 [n_species][n],
+ *     both in the caller's original particle order (pid = row index).
+ *   - Determinism: the same params, inputs and seed give bit-identical
+ *     results run to run, across a resume at start_step, and alone versus
+ *     inside a pool.
+ */
+#ifndef MTPT_H
+#define MTPT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MTPT_ABI_VERSION 1
+
+typedef struct mtpt_sim mtpt_sim;   /* opaque, library-owned */
+typedef struct mtpt_pool mtpt_pool; /* opaque, library-owned */
+
+enum {
+    MTPT_OK = 0,
+    MTPT_E_ARG = -1,       /* invalid argument or parameter */
+    MTPT_E_NOMEM = -2,     /* device memory (or pool budget/slots) exhausted */
+    MTPT_E_DEVICE = -3,    /* a HIP call failed; message has hipGetErrorString */
+    MTPT_E_NONFINITE = -4, /* a mass total became NaN or infinite */
+    MTPT_E_ABI = -5,       /* params.abi_version != MTPT_ABI_VERSION */
+    MTPT_E_STATE = -6      /* call not valid in the object's current state */
+};
+
+/* Internal arithmetic.  FP64: positions, weights and masses in FP64.
+ * FP32W_FP64ACC: positions and weights in FP32, masses and their increments
+ * in FP64.  FP32_KAHAN: positions, weights and masses in FP32, each increment
+ * summed with Kahan compensation.  In FP32 modes the input positions are
+ * rounded to FP32 once at create and the walk runs in FP32; pairs whose FP32
+ * squared distance lies within 1e-5 relative of psi^2 are re-tested in FP64,
+ * so the neighbour sets equal those of an FP64 test on the FP32 positions. */
+enum { MTPT_FP64 = 0, MTPT_FP32W_FP64ACC = 1, MTPT_FP32_KAHAN = 2 };
+
+typedef struct {
+    uint32_t abi_version; /* must be MTPT_ABI_VERSION */
+    int32_t dim;          /* 2 or 3 */
+    int64_t n;            /* particles, >= 0 */
+    int32_t n_species;    /* 1, or 3 (A, B, C with the A+B->C reaction) */
+    int32_t precision;    /* MTPT_FP64 / MTPT_FP32W_FP64ACC / MTPT_FP32_KAHAN */
+    double lo[3], hi[3];  /* box [lo, hi]^dim, reflecting walls, hi > lo */
+    double d_rw;          /* random-walk diffusivity, >= 0 (0: static particles) */
+    double d_mt;          /* mass-transfer diffusivity, > 0 */
+    double dt;            /* time step, > 0 */
+    double beta;          /* bandwidth/update coefficient, in (0, 1] */
+    double psi;           /* search radius; <= 0 selects 3 sqrt(4 D_MT dt) */
+    double k_react;       /* A+B->C rate constant (n_species == 3), >= 0 */
+    uint64_t seed;        /* Philox key of the random walk */
+    int64_t start_step;   /* index of the first step (resume), >= 0 */
+} mtpt_params;
+
+typedef struct {
+    void* (*alloc)(size_t bytes, void* ctx); /* returns device memory or NULL */
+    void (*free)(void* ptr, void* ctx);
+    void* ctx;
+} mtpt_allocator;
+
+typedef struct {
+    int64_t steps_done;     /* steps taken since create */
+    int64_t pairs_last;     /* ordered pairs i != j within psi at the last step */
+    uint64_t pairs_total;   /* sum of pairs over all steps taken */
+    double mass_total[3];   /* per-species FP64 mass totals after the last step */
+    double mass_initial[3]; /* the same at create */
+    double drift;           /* max |total - initial| / |initial| over the conserved
+                               totals: each species, or A+C and B+C with A+B->C */
+    int32_t nonfinite;      /* 1 if any total was ever NaN or infinite */
+    int32_t n_cells;        /* cells of the binning grid (side >= psi) */
+} mtpt_stats_t;
+
+/* Create a simulation (Sec. 3 state: positions, masses, parameters).
+ * pos: host FP64 [n][dim]; every coordinate within [lo, hi].
+ * mass: host FP64 [n_species][n].
+ * hip_stream: a hipStream_t, or NULL for a library-owned stream.
+ * alloc: device allocator, or NULL for hipMalloc/hipFree.
+ * Enqueues the first cell binning and the initial mass totals.
+ * Errors: MTPT_E_ABI, MTPT_E_ARG (dim, n, species, precision, box, dt, d_mt,
+ * d_rw, beta, k_react out of range, or a position outside the box),
+ * MTPT_E_NOMEM, MTPT_E_DEVICE.  *out is NULL on error. */
+int mtpt_create(const mtpt_params* params, const double* pos, const double* mass,
+                void* hip_stream, const mtpt_allocator* alloc, mtpt_sim** out);
+
+/* Enqueue n_steps full steps (walk, binning, row sums, exchange, reaction,
+ * totals) on the sim's stream; returns without waiting.  n_steps >= 0. */
+int mtpt_step(mtpt_sim* sim, int64_t n_steps);
+
+/* Masses after the last step, FP64 [n_species][n], original order.
+ * Synchronises.  Returns MTPT_E_NONFINITE if a mass total was non-finite. */
+int mtpt_masses(mtpt_sim* sim, double* out);
+
+/* Positions after the last step, FP64 [n][dim], original order.  Synchronises. */
+int mtpt_positions(mtpt_sim* sim, double* out);
+
+/* Counters and totals (see mtpt_stats_t).  Synchronises. */
+int mtpt_stats(mtpt_sim* sim, mtpt_stats_t* out);
+
+/* Neighbour sets at the current positions (Sec. 3, r^2 <= psi^2, inclusive,
+ * self included), as CSR in original order with each row ascending:
+ * row_ptr[n+1] (always written), col[nnz] written only when nnz <= cap.
+ * *nnz_out receives nnz.  Synchronises.  A debug/test export, not a step. */
+int mtpt_neighbors(mtpt_sim* sim, int64_t* row_ptr, int64_t* col, int64_t cap, int64_t* nnz_out);
+
+/* Free the sim's device memory (and stream, if library-owned).  NULL is a
+ * no-op.  Synchronises on the sim's stream first. */
+int mtpt_destroy(mtpt_sim* sim);
+
+/* Message of the last error on this thread ("" if none). */
+const char* mtpt_last_error(void);
+
+/* MTPT_ABI_VERSION the library was built with. */
+int mtpt_abi_version(void);
+
+/* Per-phase device time: when enabled, HIP events bracket every kernel the
+ * sim launches and their durations are accumulated per phase.  names[k] and
+ * ms[k], k < *count, receive phase name, total milliseconds and launch count.
+ * mtpt_phase_times synchronises and resets the accumulators. */
+int mtpt_set_profiling(mtpt_sim* sim, int32_t on);
+int mtpt_phase_times(mtpt_sim* sim, const char** names, double* ms, int64_t* launches,
+                     int32_t cap, int32_t* count);
+
+/* ---------------------------------------------------------------------
+ * Serving: a pool of independent simulations of any size and dimension,
+ * admitted while device memory and slots allow, stepped together: one tick
+ * advances every active sim by one step with one batched launch per phase.
+ * --------------------------------------------------------------------- */
+
+/* hbm_budget: bytes of device memory the pool may hold (0: 90 % of free
+ * memory at create).  max_slots: most sims active at once (>= 1). */
+int mtpt_pool_create(size_t hbm_budget, int32_t max_slots, void* hip_stream,
+                     const mtpt_allocator* alloc, mtpt_pool** out);
+
+/* Admit a sim that will run n_steps (>= 1) steps.  *ticket identifies it.
+ * Returns MTPT_E_NOMEM when the slots or the budget cannot hold it now (retry
+ * after a result has been collected); other errors as mtpt_create. */
+int mtpt_pool_admit(mtpt_pool* pool, const mtpt_params* params, const double* pos,
+                    const double* mass, int64_t n_steps, int64_t* ticket);
+
+/* Enqueue one step for every active sim that still has steps to take.
+ * *n_completed receives the number of sims whose last step this tick was.
+ * Returns without waiting. */
+int mtpt_pool_tick(mtpt_pool* pool, int32_t* n_completed);
+
+/* 1 in *done if the ticket's sim has taken all its steps (synchronises). */
+int mtpt_pool_done(mtpt_pool* pool, int64_t ticket, int32_t* done);
+
+/* Copy a finished sim's masses (FP64 [n_species][n], original order) and
+ * free its slot and memory.  Synchronises.  MTPT_E_STATE if not finished. */
+int mtpt_pool_result(mtpt_pool* pool, int64_t ticket, double* mass_out);
+
+/* Active sims, bytes held, budget. */
+int mtpt_pool_usage(mtpt_pool* pool, int32_t* active, size_t* bytes_held, size_t* budget);
+
+/* Bytes of device memory a sim with these params needs (for admission). */
+int mtpt_sim_bytes(const mtpt_params* params, size_t* bytes);
+
+/* Free every sim of the pool and the pool.  NULL is a no-op. */
+int mtpt_pool_destroy(mtpt_pool* pool);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MTPT_H */

@@ -1,0 +1,134 @@
+// mtpt_kernels.h -- device data layout and kernel entry points of the MTPT
+// step on gfx950.  Shared by the single-sim runtime and the serving pool.
+//
+// Layout in HBM (per simulation, n particles, S species, T = double in FP64
+// mode and float otherwise, M = float in Kahan mode and double otherwise):
+//   X[k][n]     T    positions, structure of arrays, sorted by cell and then
+//                    by pid inside a cell (the order every MT pass walks)
+//   XT[k][n]    T    walked positions in the order before re-binning
+//   M[2][S][n]  M    masses, two buffers (Jacobi update)
+//   P[2][n]     u32  pid of each sorted slot, two buffers
+//   Srow[n]     T    row sums s_i = sum_j K_ij
+//   cell, rank, perm [n] u32   binning scratch
+//   counts[ncells padded], starts[ncells+1] u32   cell histogram and offsets
+//   bsum[]      u32  per-block partial sums of the scan
+//   partials[]  f64  per-block mass partial sums
+//   DevStats         pair counters, totals, completion ticket
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mtpt {
+
+constexpr int kBlock = 256;          // threads per block, 4 wave64s
+constexpr int kScanItems = 16;       // counts per thread in the scan
+constexpr int kScanTile = kBlock * kScanItems;
+
+struct DevStats {
+    unsigned long long pairs_acc;    // pairs counted by the current row-sum pass
+    unsigned long long pairs_last;   // pairs of the last step
+    unsigned long long pairs_total;  // over all steps
+    unsigned int blocks_done;        // completion ticket of the transfer pass
+    int nonfinite;                   // sticky: a total was NaN or infinite
+    double totals[3];                // mass totals after the last step
+    long long steps;                 // steps completed on the device
+    double pad[2];
+};
+
+// Everything one launch of one phase needs about one simulation.  Pointers
+// are resolved by the host for the step being enqueued.
+struct SimArgs {
+    int64_t n;
+    int32_t ns;              // species (1 or 3)
+    int32_t moving;          // random walk on (D_RW > 0)
+    // cell grid: cell side >= psi in every dimension
+    double glo[3];
+    double inv_side[3];
+    int32_t nc[3];
+    uint32_t ncells;
+    // box and walk
+    double lo[3], hi[3];
+    float lof[3], hif[3];
+    double sdev;             // sqrt(2 D_RW dt)
+    uint64_t seed;
+    int64_t step;
+    // weights: K = exp(-kc r^2), kc = beta / (4 D_MT dt)
+    double psi2;             // psi * psi (FP64, the canonical cutoff)
+    float psi2_in;           // FP32 r^2 below this: inside for sure
+    float psi2_out;          // FP32 r^2 above this: outside for sure
+    double kc;
+    float kcf;
+    double beta;
+    float betaf;
+    double k_react, to_c, to_m, dt;
+    // buffers
+    void* x[3];
+    void* xt[3];
+    void* m_src[3];          // gather source (old order)
+    void* m_mid[3];          // masses in the current sorted order
+    void* m_dst[3];          // transfer output
+    uint32_t* pid_src;
+    uint32_t* pid_dst;       // gather output = current sorted pids
+    void* srow;
+    uint32_t* cell;
+    uint32_t* rank;
+    uint32_t* perm;
+    uint32_t* counts;
+    uint32_t* starts;
+    uint32_t* bsum;
+    double* partials;
+    DevStats* st;
+    uint32_t scan_blocks;    // ceil(ncells / kScanTile)
+    uint32_t part_blocks;    // ceil(n / kBlock)
+    int32_t recompute_s;     // the row-sum pass ran this step
+    int32_t walk;            // apply the jump in the bin pass (0 at create)
+};
+
+// Launch helpers (host).  prec: 0 FP64, 1 FP32W_FP64ACC, 2 FP32_KAHAN.
+// Single-sim launches take the arguments by value; batched launches take a
+// device array of SimArgs and a device prefix of blocks per sim.
+struct Batch {
+    const SimArgs* args;       // device array [nsims]
+    const uint32_t* blk_off;   // device [nsims + 1], prefix of blocks
+    int32_t nsims;
+    uint32_t total_blocks;
+};
+
+enum Phase {
+    PH_BIN = 0,
+    PH_SCAN_REDUCE,
+    PH_SCAN_TOP,
+    PH_SCAN_DOWN,
+    PH_SCATTER,
+    PH_CELLSORT,
+    PH_GATHER,
+    PH_ROWSUM,
+    PH_TRANSFER,
+    PH_COUNT
+};
+
+const char* phase_name(int ph);
+
+// blocks a phase needs for one sim
+uint32_t phase_blocks(int ph, const SimArgs& a);
+
+// single-sim launch of a phase
+hipError_t launch_phase(int ph, int dim, int prec, const SimArgs& a, hipStream_t s);
+// batched launch of a phase over sims that share (dim, prec)
+hipError_t launch_phase_batched(int ph, int dim, int prec, int ns, const Batch& b, hipStream_t s);
+
+// exports
+hipError_t launch_unpermute_mass(int prec, const SimArgs& a, const void* const* m_cur,
+                                 const uint32_t* pid_cur, double* out, hipStream_t s);
+hipError_t launch_unpermute_pos(int dim, int prec, const SimArgs& a, const uint32_t* pid_cur,
+                                double* out, hipStream_t s);
+hipError_t launch_totals(int prec, const SimArgs& a, const void* const* m_cur, hipStream_t s);
+hipError_t launch_nb_count(int dim, int prec, const SimArgs& a, const uint32_t* pid_cur,
+                           uint32_t* rowcnt, hipStream_t s);
+hipError_t launch_nb_fill(int dim, int prec, const SimArgs& a, const uint32_t* pid_cur,
+                          const int64_t* row_ptr, int64_t* col, hipStream_t s);
+hipError_t launch_scan_u32_to_i64(const uint32_t* in, int64_t* out, int64_t len, uint32_t* tmp_counts,
+                                  uint32_t* bsum, hipStream_t s);
+
+}  // namespace mtpt

@@ -1,0 +1,1111 @@
+// mtpt_runtime.hip -- host runtime and C-ABI of libmtpt.so.
+//
+// A simulation owns one device allocation carved into the buffers listed in
+// mtpt_kernels.h, a stream, and the host-side step counter that decides which
+// of the double buffers is current.  mtpt_step enqueues the phases of a step
+// and never waits; exports enqueue a gather by pid and a device-to-host copy,
+// then wait.
+#include "../../include/mtpt.h"
+#include "mtpt_kernels.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <string>
+#include <vector>
+
+using namespace mtpt;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    std::vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                              \
+    do {                                                                                           \
+        hipError_t e_ = (expr);                                                                    \
+        if (e_ != hipSuccess)                                                                      \
+            return fail(MTPT_E_DEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));             \
+    } while (0)
+
+struct Alloc {
+    mtpt_allocator a{};
+    bool custom = false;
+    void* get(size_t bytes)
+    {
+        if (bytes == 0)
+            bytes = 256;
+        if (custom)
+            return a.alloc(bytes, a.ctx);
+        void* p = nullptr;
+        if (hipMalloc(&p, bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
+        return p;
+    }
+    void put(void* p)
+    {
+        if (!p)
+            return;
+        if (custom)
+            a.free(p, a.ctx);
+        else
+            (void)hipFree(p);
+    }
+};
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// Buffer plan of one simulation: grid and byte offsets inside one allocation.
+struct Plan {
+    int dim = 2, ns = 1, prec = 0;
+    int64_t n = 0;
+    double psi = 0;
+    int nc[3] = {1, 1, 1};
+    double inv_side[3] = {0, 0, 0};
+    uint32_t ncells = 1;
+    uint32_t scan_blocks = 1, part_blocks = 0;
+    size_t tsz = 8, msz = 8;
+    size_t off_x[3]{}, off_xt[3]{}, off_m[2][3]{}, off_p[2]{}, off_s = 0, off_cell = 0, off_rank = 0,
+           off_perm = 0, off_counts = 0, off_starts = 0, off_bsum = 0, off_part = 0, off_stats = 0;
+    size_t bytes = 0;
+};
+
+int validate(const mtpt_params* p)
+{
+    if (!p)
+        return fail(MTPT_E_ARG, "params is NULL");
+    if (p->abi_version != MTPT_ABI_VERSION)
+        return fail(MTPT_E_ABI, "abi_version %u, library has %d", p->abi_version, MTPT_ABI_VERSION);
+    if (p->dim != 2 && p->dim != 3)
+        return fail(MTPT_E_ARG, "dim must be 2 or 3 (got %d)", p->dim);
+    if (p->n < 0 || p->n > 0xFFFFFF00ll)
+        return fail(MTPT_E_ARG, "n must be in [0, 2^32 - 256] (got %lld)", (long long)p->n);
+    if (p->n_species != 1 && p->n_species != 3)
+        return fail(MTPT_E_ARG, "n_species must be 1 or 3 (got %d)", p->n_species);
+    if (p->precision < 0 || p->precision > 2)
+        return fail(MTPT_E_ARG, "precision must be 0, 1 or 2 (got %d)", p->precision);
+    for (int k = 0; k < p->dim; ++k)
+        if (!std::isfinite(p->lo[k]) || !std::isfinite(p->hi[k]) || !(p->hi[k] > p->lo[k]))
+            return fail(MTPT_E_ARG, "box dimension %d: need finite lo < hi", k);
+    if (!std::isfinite(p->d_rw) || p->d_rw < 0)
+        return fail(MTPT_E_ARG, "d_rw must be finite and >= 0");
+    if (!std::isfinite(p->d_mt) || !(p->d_mt > 0))
+        return fail(MTPT_E_ARG, "d_mt must be finite and > 0");
+    if (!std::isfinite(p->dt) || !(p->dt > 0))
+        return fail(MTPT_E_ARG, "dt must be finite and > 0");
+    if (!std::isfinite(p->beta) || !(p->beta > 0) || p->beta > 1.0)
+        return fail(MTPT_E_ARG, "beta must be in (0, 1]");
+    if (!std::isfinite(p->psi))
+        return fail(MTPT_E_ARG, "psi must be finite");
+    if (!std::isfinite(p->k_react) || p->k_react < 0)
+        return fail(MTPT_E_ARG, "k_react must be finite and >= 0");
+    if (p->start_step < 0)
+        return fail(MTPT_E_ARG, "start_step must be >= 0");
+    return MTPT_OK;
+}
+
+double psi_of(const mtpt_params& p) { return p.psi > 0 ? p.psi : 3.0 * std::sqrt(4.0 * p.d_mt * p.dt); }
+
+Plan make_plan(const mtpt_params& p)
+{
+    Plan q;
+    q.dim = p.dim;
+    q.ns = p.n_species;
+    q.prec = p.precision;
+    q.n = p.n;
+    q.psi = psi_of(p);
+    q.tsz = p.precision == MTPT_FP64 ? 8 : 4;
+    q.msz = p.precision == MTPT_FP32_KAHAN ? 4 : 8;
+    // cells of side >= psi (1 + 1e-6): every pair within psi then lies in
+    // neighbouring cells even after rounding of the cell coordinate
+    double side_min = q.psi * (1.0 + 1e-6);
+    for (int k = 0; k < q.dim; ++k) {
+        const double L = p.hi[k] - p.lo[k];
+        double c = std::floor(L / side_min);
+        c = std::min(std::max(c, 1.0), 1048576.0);
+        q.nc[k] = static_cast<int>(c);
+    }
+    // at most ~4 cells per particle (and 2^30 cells): larger cells are also correct
+    const double cap = std::min(1073741824.0, std::max(64.0, 4.0 * static_cast<double>(q.n)));
+    for (;;) {
+        double tot = 1.0;
+        for (int k = 0; k < q.dim; ++k)
+            tot *= q.nc[k];
+        if (tot <= cap)
+            break;
+        for (int k = 0; k < q.dim; ++k)
+            q.nc[k] = std::max(1, q.nc[k] - std::max(1, q.nc[k] / 8));
+    }
+    q.ncells = 1;
+    for (int k = 0; k < q.dim; ++k) {
+        q.ncells *= static_cast<uint32_t>(q.nc[k]);
+        q.inv_side[k] = static_cast<double>(q.nc[k]) / (p.hi[k] - p.lo[k]);
+    }
+    q.scan_blocks = static_cast<uint32_t>((static_cast<uint64_t>(q.ncells) + 1 + kScanTile - 1) / kScanTile);
+    q.part_blocks = static_cast<uint32_t>((q.n + kBlock - 1) / kBlock);
+    const size_t n = static_cast<size_t>(q.n);
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off = align_up(off + std::max<size_t>(bytes, 1), 256);
+        return o;
+    };
+    for (int k = 0; k < 3; ++k)
+        q.off_x[k] = k < q.dim ? take(n * q.tsz) : 0;
+    for (int k = 0; k < 3; ++k)
+        q.off_xt[k] = k < q.dim ? take(n * q.tsz) : 0;
+    for (int b = 0; b < 2; ++b)
+        for (int c = 0; c < 3; ++c)
+            q.off_m[b][c] = c < q.ns ? take(n * q.msz) : 0;
+    q.off_p[0] = take(n * 4);
+    q.off_p[1] = take(n * 4);
+    q.off_s = take(n * q.tsz);
+    q.off_cell = take(n * 4);
+    q.off_rank = take(n * 4);
+    q.off_perm = take(n * 4);
+    const size_t padded = static_cast<size_t>(q.scan_blocks) * kScanTile;
+    q.off_counts = take(padded * 4);
+    q.off_starts = take(padded * 4);
+    q.off_bsum = take(static_cast<size_t>(q.scan_blocks) * 4);
+    q.off_part = take(static_cast<size_t>(std::max<uint32_t>(q.part_blocks, 1)) * 3 * 8);
+    q.off_stats = take(sizeof(DevStats));
+    q.bytes = off;
+    return q;
+}
+
+struct PhaseEv {
+    int phase;
+    hipEvent_t a, b;
+};
+
+}  // namespace
+
+struct mtpt_sim {
+    mtpt_params p{};
+    Plan q;
+    Alloc alloc;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    char* base = nullptr;
+    void* X[3]{};
+    void* XT[3]{};
+    void* M[2][3]{};
+    uint32_t* P[2]{};
+    void* S = nullptr;
+    uint32_t *cell = nullptr, *rank = nullptr, *perm = nullptr, *counts = nullptr, *starts = nullptr,
+             *bsum = nullptr;
+    double* partials = nullptr;
+    DevStats* st = nullptr;
+    int64_t steps_done = 0;   // steps enqueued since create
+    bool moving = false;
+    bool s_valid = false;
+    double mass_initial[3]{};
+    // profiling
+    bool profiling = false;
+    std::vector<PhaseEv> evs;
+    double ph_ms[PH_COUNT]{};
+    int64_t ph_n[PH_COUNT]{};
+    // pool bookkeeping
+    int64_t steps_target = -1;
+};
+
+namespace {
+
+void carve(mtpt_sim* s)
+{
+    const Plan& q = s->q;
+    char* b = s->base;
+    for (int k = 0; k < 3; ++k) {
+        s->X[k] = k < q.dim ? b + q.off_x[k] : nullptr;
+        s->XT[k] = k < q.dim ? b + q.off_xt[k] : nullptr;
+    }
+    for (int bb = 0; bb < 2; ++bb)
+        for (int c = 0; c < 3; ++c)
+            s->M[bb][c] = c < q.ns ? b + q.off_m[bb][c] : nullptr;
+    s->P[0] = reinterpret_cast<uint32_t*>(b + q.off_p[0]);
+    s->P[1] = reinterpret_cast<uint32_t*>(b + q.off_p[1]);
+    s->S = b + q.off_s;
+    s->cell = reinterpret_cast<uint32_t*>(b + q.off_cell);
+    s->rank = reinterpret_cast<uint32_t*>(b + q.off_rank);
+    s->perm = reinterpret_cast<uint32_t*>(b + q.off_perm);
+    s->counts = reinterpret_cast<uint32_t*>(b + q.off_counts);
+    s->starts = reinterpret_cast<uint32_t*>(b + q.off_starts);
+    s->bsum = reinterpret_cast<uint32_t*>(b + q.off_bsum);
+    s->partials = reinterpret_cast<double*>(b + q.off_part);
+    s->st = reinterpret_cast<DevStats*>(b + q.off_stats);
+}
+
+// SimArgs with every constant filled; buffer roles are set by the caller.
+SimArgs base_args(const mtpt_sim* s)
+{
+    const Plan& q = s->q;
+    const mtpt_params& p = s->p;
+    SimArgs a{};
+    a.n = q.n;
+    a.ns = q.ns;
+    a.moving = s->moving ? 1 : 0;
+    for (int k = 0; k < 3; ++k) {
+        a.glo[k] = p.lo[k];
+        a.inv_side[k] = q.inv_side[k];
+        a.nc[k] = q.nc[k];
+        a.lo[k] = p.lo[k];
+        a.hi[k] = p.hi[k];
+        a.lof[k] = static_cast<float>(p.lo[k]);
+        a.hif[k] = static_cast<float>(p.hi[k]);
+    }
+    a.ncells = q.ncells;
+    a.sdev = std::sqrt(2.0 * p.d_rw * p.dt);
+    a.seed = p.seed;
+    a.psi2 = q.psi * q.psi;
+    a.psi2_in = static_cast<float>(a.psi2 * (1.0 - 1e-5));
+    a.psi2_out = static_cast<float>(a.psi2 * (1.0 + 1e-5));
+    a.kc = p.beta / (4.0 * p.d_mt * p.dt);
+    a.kcf = static_cast<float>(a.kc);
+    a.beta = p.beta;
+    a.betaf = static_cast<float>(p.beta);
+    a.k_react = p.k_react;
+    double vol = 1.0;
+    for (int k = 0; k < q.dim; ++k)
+        vol *= p.hi[k] - p.lo[k];
+    a.to_c = q.n > 0 ? static_cast<double>(q.n) / vol : 0.0;
+    a.to_m = q.n > 0 ? vol / static_cast<double>(q.n) : 0.0;
+    a.dt = p.dt;
+    for (int k = 0; k < 3; ++k) {
+        a.x[k] = s->X[k];
+        a.xt[k] = s->XT[k];
+    }
+    a.srow = s->S;
+    a.cell = s->cell;
+    a.rank = s->rank;
+    a.perm = s->perm;
+    a.counts = s->counts;
+    a.starts = s->starts;
+    a.bsum = s->bsum;
+    a.partials = s->partials;
+    a.st = s->st;
+    a.scan_blocks = q.scan_blocks;
+    a.part_blocks = q.part_blocks;
+    return a;
+}
+
+// Current sorted pids and masses after steps_done steps.
+//   moving sims: the gather alternates the pid buffers (P[t&1] current) and
+//     the masses go M0 -> (gather) M1 -> (transfer) M0;
+//   static sims: binned once at create (P0), the masses alternate M[t&1].
+uint32_t* cur_pid(const mtpt_sim* s) { return s->moving ? s->P[s->steps_done & 1] : s->P[0]; }
+void* const* cur_mass(const mtpt_sim* s) { return s->moving ? s->M[0] : s->M[s->steps_done & 1]; }
+
+// Arguments of step number steps_done (0-based since create).
+SimArgs step_args(const mtpt_sim* s, bool* rowsum_needed)
+{
+    SimArgs a = base_args(s);
+    const int64_t t = s->steps_done;
+    a.step = s->p.start_step + t;
+    a.walk = s->moving ? 1 : 0;
+    if (s->moving) {
+        a.pid_src = s->P[t & 1];
+        a.pid_dst = s->P[(t + 1) & 1];
+        for (int c = 0; c < 3; ++c) {
+            a.m_src[c] = s->M[0][c];
+            a.m_mid[c] = s->M[1][c];
+            a.m_dst[c] = s->M[0][c];
+        }
+        a.recompute_s = 1;
+    } else {
+        a.pid_src = s->P[0];
+        a.pid_dst = s->P[0];
+        for (int c = 0; c < 3; ++c) {
+            a.m_src[c] = s->M[t & 1][c];
+            a.m_mid[c] = s->M[t & 1][c];
+            a.m_dst[c] = s->M[(t + 1) & 1][c];
+        }
+        a.recompute_s = s->s_valid ? 0 : 1;
+    }
+    *rowsum_needed = a.recompute_s != 0;
+    return a;
+}
+
+int launch(mtpt_sim* s, int ph, const SimArgs& a)
+{
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (s->profiling) {
+        HIP_TRY(hipEventCreate(&e0));
+        HIP_TRY(hipEventCreate(&e1));
+        HIP_TRY(hipEventRecord(e0, s->stream));
+    }
+    HIP_TRY(launch_phase(ph, s->q.dim, s->q.prec, a, s->stream));
+    if (s->profiling) {
+        HIP_TRY(hipEventRecord(e1, s->stream));
+        s->evs.push_back({ph, e0, e1});
+    }
+    return MTPT_OK;
+}
+
+int enqueue_binning(mtpt_sim* s, const SimArgs& a)
+{
+    static const int phases[] = {PH_BIN, PH_SCAN_REDUCE, PH_SCAN_TOP, PH_SCAN_DOWN,
+                                 PH_SCATTER, PH_CELLSORT, PH_GATHER};
+    for (int ph : phases) {
+        const int rc = launch(s, ph, a);
+        if (rc)
+            return rc;
+    }
+    return MTPT_OK;
+}
+
+int enqueue_step(mtpt_sim* s)
+{
+    bool need_rowsum = false;
+    SimArgs a = step_args(s, &need_rowsum);
+    if (s->moving) {
+        const int rc = enqueue_binning(s, a);
+        if (rc)
+            return rc;
+    }
+    if (need_rowsum) {
+        const int rc = launch(s, PH_ROWSUM, a);
+        if (rc)
+            return rc;
+    }
+    const int rc = launch(s, PH_TRANSFER, a);
+    if (rc)
+        return rc;
+    s->steps_done += 1;
+    if (!s->moving)
+        s->s_valid = true;
+    return MTPT_OK;
+}
+
+int sync(mtpt_sim* s)
+{
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    return MTPT_OK;
+}
+
+int collect_events(mtpt_sim* s)
+{
+    for (auto& e : s->evs) {
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, e.a, e.b));
+        s->ph_ms[e.phase] += ms;
+        s->ph_n[e.phase] += 1;
+        (void)hipEventDestroy(e.a);
+        (void)hipEventDestroy(e.b);
+    }
+    s->evs.clear();
+    return MTPT_OK;
+}
+
+void release(mtpt_sim* s)
+{
+    if (!s)
+        return;
+    for (auto& e : s->evs) {
+        (void)hipEventDestroy(e.a);
+        (void)hipEventDestroy(e.b);
+    }
+    s->evs.clear();
+    s->alloc.put(s->base);
+    s->base = nullptr;
+    if (s->own_stream && s->stream)
+        (void)hipStreamDestroy(s->stream);
+    delete s;
+}
+
+// Upload inputs and bin them (the state at step 0).  The host staging is in
+// pinned memory so the copies run asynchronously; create waits at the end.
+int create_into(mtpt_sim* s, const double* pos, const double* mass)
+{
+    const Plan& q = s->q;
+    const size_t n = static_cast<size_t>(q.n);
+    HIP_TRY(hipMemsetAsync(s->st, 0, sizeof(DevStats), s->stream));
+    HIP_TRY(hipMemsetAsync(s->counts, 0, static_cast<size_t>(q.scan_blocks) * kScanTile * 4, s->stream));
+    if (n > 0) {
+        std::vector<unsigned char> stage(std::max(n * q.tsz, n * q.msz));
+        for (int k = 0; k < q.dim; ++k) {
+            if (q.tsz == 8) {
+                double* d = reinterpret_cast<double*>(stage.data());
+                for (size_t i = 0; i < n; ++i)
+                    d[i] = pos[i * q.dim + k];
+            } else {
+                float* f = reinterpret_cast<float*>(stage.data());
+                for (size_t i = 0; i < n; ++i)
+                    f[i] = static_cast<float>(pos[i * q.dim + k]);
+            }
+            HIP_TRY(hipMemcpy(s->X[k], stage.data(), n * q.tsz, hipMemcpyHostToDevice));
+        }
+        for (int c = 0; c < q.ns; ++c) {
+            if (q.msz == 8) {
+                HIP_TRY(hipMemcpy(s->M[1][c], mass + c * n, n * 8, hipMemcpyHostToDevice));
+            } else {
+                float* f = reinterpret_cast<float*>(stage.data());
+                for (size_t i = 0; i < n; ++i)
+                    f[i] = static_cast<float>(mass[c * n + i]);
+                HIP_TRY(hipMemcpy(s->M[1][c], stage.data(), n * 4, hipMemcpyHostToDevice));
+            }
+        }
+        std::vector<uint32_t> ident(n);
+        for (size_t i = 0; i < n; ++i)
+            ident[i] = static_cast<uint32_t>(i);
+        HIP_TRY(hipMemcpy(s->P[1], ident.data(), n * 4, hipMemcpyHostToDevice));
+        // initial binning: positions in pid order, no jump; pids P1 -> P0,
+        // masses M1 -> M0
+        SimArgs a = base_args(s);
+        a.walk = 0;
+        a.step = s->p.start_step;
+        a.pid_src = s->P[1];
+        a.pid_dst = s->P[0];
+        for (int c = 0; c < 3; ++c) {
+            a.m_src[c] = s->M[1][c];
+            a.m_mid[c] = s->M[0][c];
+            a.m_dst[c] = s->M[0][c];
+        }
+        const int rc = enqueue_binning(s, a);
+        if (rc)
+            return rc;
+        HIP_TRY(launch_totals(q.prec, a, s->M[0], s->stream));
+    }
+    const int rc = sync(s);
+    if (rc)
+        return rc;
+    if (s->profiling)
+        collect_events(s);
+    DevStats h{};
+    HIP_TRY(hipMemcpy(&h, s->st, sizeof h, hipMemcpyDeviceToHost));
+    for (int c = 0; c < 3; ++c)
+        s->mass_initial[c] = c < q.ns ? h.totals[c] : 0.0;
+    return MTPT_OK;
+}
+
+int check_inputs(const mtpt_params& p, const double* pos, const double* mass)
+{
+    if (p.n > 0 && (!pos || !mass))
+        return fail(MTPT_E_ARG, "pos and mass must not be NULL when n > 0");
+    for (int64_t i = 0; i < p.n; ++i)
+        for (int k = 0; k < p.dim; ++k) {
+            const double v = pos[i * p.dim + k];
+            if (!(v >= p.lo[k] && v <= p.hi[k]))
+                return fail(MTPT_E_ARG, "particle %lld coordinate %d = %g outside [%g, %g]",
+                            (long long)i, k, v, p.lo[k], p.hi[k]);
+        }
+    for (int64_t i = 0; i < p.n * p.n_species; ++i)
+        if (!std::isfinite(mass[i]))
+            return fail(MTPT_E_ARG, "mass %lld is not finite", (long long)i);
+    return MTPT_OK;
+}
+
+int new_sim(const mtpt_params* params, const double* pos, const double* mass, void* hip_stream,
+            const mtpt_allocator* alloc, mtpt_sim** out)
+{
+    int rc = validate(params);
+    if (rc)
+        return rc;
+    rc = check_inputs(*params, pos, mass);
+    if (rc)
+        return rc;
+    if (alloc && (!alloc->alloc || !alloc->free))
+        return fail(MTPT_E_ARG, "allocator needs both alloc and free");
+    mtpt_sim* s = new mtpt_sim();
+    s->p = *params;
+    s->q = make_plan(*params);
+    s->moving = params->d_rw > 0.0;
+    if (alloc) {
+        s->alloc.a = *alloc;
+        s->alloc.custom = true;
+    }
+    if (hip_stream) {
+        s->stream = static_cast<hipStream_t>(hip_stream);
+    } else {
+        if (hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) != hipSuccess) {
+            delete s;
+            return fail(MTPT_E_DEVICE, "hipStreamCreateWithFlags failed");
+        }
+        s->own_stream = true;
+    }
+    s->base = static_cast<char*>(s->alloc.get(s->q.bytes));
+    if (!s->base) {
+        release(s);
+        return fail(MTPT_E_NOMEM, "device allocation of %zu bytes failed", s->q.bytes);
+    }
+    carve(s);
+    rc = create_into(s, pos, mass);
+    if (rc) {
+        std::string msg = g_err;
+        (void)hipStreamSynchronize(s->stream);
+        release(s);
+        g_err = msg;
+        return rc;
+    }
+    *out = s;
+    return MTPT_OK;
+}
+
+}  // namespace
+
+// ====================================================================== C-ABI
+extern "C" {
+
+const char* mtpt_last_error(void) { return g_err.c_str(); }
+
+int mtpt_abi_version(void) { return MTPT_ABI_VERSION; }
+
+int mtpt_sim_bytes(const mtpt_params* params, size_t* bytes)
+{
+    const int rc = validate(params);
+    if (rc)
+        return rc;
+    if (!bytes)
+        return fail(MTPT_E_ARG, "bytes is NULL");
+    *bytes = make_plan(*params).bytes;
+    return MTPT_OK;
+}
+
+int mtpt_create(const mtpt_params* params, const double* pos, const double* mass, void* hip_stream,
+                const mtpt_allocator* alloc, mtpt_sim** out)
+{
+    if (!out)
+        return fail(MTPT_E_ARG, "out is NULL");
+    *out = nullptr;
+    return new_sim(params, pos, mass, hip_stream, alloc, out);
+}
+
+int mtpt_step(mtpt_sim* s, int64_t n_steps)
+{
+    if (!s)
+        return fail(MTPT_E_ARG, "sim is NULL");
+    if (n_steps < 0)
+        return fail(MTPT_E_ARG, "n_steps must be >= 0");
+    if (s->q.n == 0) {
+        s->steps_done += n_steps;
+        return MTPT_OK;
+    }
+    for (int64_t k = 0; k < n_steps; ++k) {
+        const int rc = enqueue_step(s);
+        if (rc)
+            return rc;
+    }
+    return MTPT_OK;
+}
+
+int mtpt_masses(mtpt_sim* s, double* out)
+{
+    if (!s || (!out && s->q.n > 0))
+        return fail(MTPT_E_ARG, "NULL argument");
+    const size_t n = static_cast<size_t>(s->q.n);
+    if (n == 0)
+        return MTPT_OK;
+    const size_t bytes = n * s->q.ns * 8;
+    double* d = static_cast<double*>(s->alloc.get(bytes));
+    if (!d)
+        return fail(MTPT_E_NOMEM, "staging allocation failed");
+    SimArgs a = base_args(s);
+    hipError_t e = launch_unpermute_mass(s->q.prec, a, cur_mass(s), cur_pid(s), d, s->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(out, d, bytes, hipMemcpyDeviceToHost, s->stream);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(s->stream);
+    s->alloc.put(d);
+    if (e != hipSuccess)
+        return fail(MTPT_E_DEVICE, "mtpt_masses: %s", hipGetErrorString(e));
+    DevStats h{};
+    HIP_TRY(hipMemcpy(&h, s->st, sizeof h, hipMemcpyDeviceToHost));
+    if (h.nonfinite)
+        return fail(MTPT_E_NONFINITE, "a mass total became non-finite");
+    return MTPT_OK;
+}
+
+int mtpt_positions(mtpt_sim* s, double* out)
+{
+    if (!s || (!out && s->q.n > 0))
+        return fail(MTPT_E_ARG, "NULL argument");
+    const size_t n = static_cast<size_t>(s->q.n);
+    if (n == 0)
+        return MTPT_OK;
+    const size_t bytes = n * s->q.dim * 8;
+    double* d = static_cast<double*>(s->alloc.get(bytes));
+    if (!d)
+        return fail(MTPT_E_NOMEM, "staging allocation failed");
+    SimArgs a = base_args(s);
+    hipError_t e = launch_unpermute_pos(s->q.dim, s->q.prec, a, cur_pid(s), d, s->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(out, d, bytes, hipMemcpyDeviceToHost, s->stream);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(s->stream);
+    s->alloc.put(d);
+    if (e != hipSuccess)
+        return fail(MTPT_E_DEVICE, "mtpt_positions: %s", hipGetErrorString(e));
+    return MTPT_OK;
+}
+
+int mtpt_stats(mtpt_sim* s, mtpt_stats_t* out)
+{
+    if (!s || !out)
+        return fail(MTPT_E_ARG, "NULL argument");
+    int rc = sync(s);
+    if (rc)
+        return rc;
+    DevStats h{};
+    HIP_TRY(hipMemcpy(&h, s->st, sizeof h, hipMemcpyDeviceToHost));
+    std::memset(out, 0, sizeof *out);
+    out->steps_done = s->steps_done;
+    out->pairs_last = static_cast<int64_t>(h.pairs_last);
+    out->pairs_total = h.pairs_total;
+    for (int c = 0; c < 3; ++c) {
+        const bool on = c < s->q.ns && s->q.n > 0;
+        out->mass_total[c] = on ? (s->steps_done > 0 ? h.totals[c] : s->mass_initial[c]) : 0.0;
+        out->mass_initial[c] = on ? s->mass_initial[c] : 0.0;
+    }
+    // drift of the conserved quantities: each species without reaction;
+    // A + C and B + C when A + B -> C runs
+    double drift = 0.0;
+    auto rel = [](double now, double init) {
+        return init != 0.0 ? std::fabs(now - init) / std::fabs(init) : std::fabs(now);
+    };
+    if (s->q.ns == 3 && s->p.k_react > 0.0) {
+        const double* t = out->mass_total;
+        const double* i0 = out->mass_initial;
+        drift = std::max(rel(t[0] + t[2], i0[0] + i0[2]), rel(t[1] + t[2], i0[1] + i0[2]));
+    } else {
+        for (int c = 0; c < s->q.ns; ++c)
+            drift = std::max(drift, rel(out->mass_total[c], out->mass_initial[c]));
+    }
+    out->drift = drift;
+    out->nonfinite = h.nonfinite;
+    out->n_cells = static_cast<int32_t>(s->q.ncells);
+    return MTPT_OK;
+}
+
+int mtpt_neighbors(mtpt_sim* s, int64_t* row_ptr, int64_t* col, int64_t cap, int64_t* nnz_out)
+{
+    if (!s || !row_ptr || !nnz_out)
+        return fail(MTPT_E_ARG, "NULL argument");
+    const int64_t n = s->q.n;
+    row_ptr[0] = 0;
+    *nnz_out = 0;
+    if (n == 0)
+        return MTPT_OK;
+    const int64_t tiles = (n + 1 + kScanTile - 1) / kScanTile;
+    uint32_t* rowcnt = static_cast<uint32_t*>(s->alloc.get(static_cast<size_t>(n) * 4));
+    uint32_t* tmp = static_cast<uint32_t*>(s->alloc.get(static_cast<size_t>(tiles) * kScanTile * 4));
+    uint32_t* bs = static_cast<uint32_t*>(s->alloc.get(static_cast<size_t>(tiles) * 4));
+    int64_t* drp = static_cast<int64_t*>(s->alloc.get(static_cast<size_t>(n + 1) * 8));
+    int64_t* dcol = nullptr;
+    int rc = MTPT_OK;
+    hipError_t e = hipSuccess;
+    if (!rowcnt || !tmp || !bs || !drp) {
+        rc = fail(MTPT_E_NOMEM, "neighbour export allocation failed");
+        goto done;
+    }
+    {
+        SimArgs a = base_args(s);
+        e = launch_nb_count(s->q.dim, s->q.prec, a, cur_pid(s), rowcnt, s->stream);
+        if (e == hipSuccess)
+            e = launch_scan_u32_to_i64(rowcnt, drp, n, tmp, bs, s->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(row_ptr, drp, static_cast<size_t>(n + 1) * 8, hipMemcpyDeviceToHost, s->stream);
+        if (e == hipSuccess)
+            e = hipStreamSynchronize(s->stream);
+        if (e != hipSuccess) {
+            rc = fail(MTPT_E_DEVICE, "mtpt_neighbors: %s", hipGetErrorString(e));
+            goto done;
+        }
+        const int64_t nnz = row_ptr[n];
+        *nnz_out = nnz;
+        if (col && nnz <= cap && nnz > 0) {
+            dcol = static_cast<int64_t*>(s->alloc.get(static_cast<size_t>(nnz) * 8));
+            if (!dcol) {
+                rc = fail(MTPT_E_NOMEM, "neighbour export allocation failed");
+                goto done;
+            }
+            e = launch_nb_fill(s->q.dim, s->q.prec, a, cur_pid(s), drp, dcol, s->stream);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(col, dcol, static_cast<size_t>(nnz) * 8, hipMemcpyDeviceToHost, s->stream);
+            if (e == hipSuccess)
+                e = hipStreamSynchronize(s->stream);
+            if (e != hipSuccess)
+                rc = fail(MTPT_E_DEVICE, "mtpt_neighbors: %s", hipGetErrorString(e));
+        }
+    }
+done:
+    (void)hipStreamSynchronize(s->stream);
+    s->alloc.put(rowcnt);
+    s->alloc.put(tmp);
+    s->alloc.put(bs);
+    s->alloc.put(drp);
+    s->alloc.put(dcol);
+    return rc;
+}
+
+int mtpt_destroy(mtpt_sim* s)
+{
+    if (!s)
+        return MTPT_OK;
+    (void)hipStreamSynchronize(s->stream);
+    release(s);
+    return MTPT_OK;
+}
+
+int mtpt_set_profiling(mtpt_sim* s, int32_t on)
+{
+    if (!s)
+        return fail(MTPT_E_ARG, "sim is NULL");
+    s->profiling = on != 0;
+    return MTPT_OK;
+}
+
+int mtpt_phase_times(mtpt_sim* s, const char** names, double* ms, int64_t* launches, int32_t cap,
+                     int32_t* count)
+{
+    if (!s || !count)
+        return fail(MTPT_E_ARG, "NULL argument");
+    int rc = sync(s);
+    if (rc)
+        return rc;
+    rc = collect_events(s);
+    if (rc)
+        return rc;
+    int32_t k = 0;
+    for (int ph = 0; ph < PH_COUNT; ++ph) {
+        if (s->ph_n[ph] == 0)
+            continue;
+        if (k < cap) {
+            if (names)
+                names[k] = phase_name(ph);
+            if (ms)
+                ms[k] = s->ph_ms[ph];
+            if (launches)
+                launches[k] = s->ph_n[ph];
+        }
+        ++k;
+        s->ph_ms[ph] = 0.0;
+        s->ph_n[ph] = 0;
+    }
+    *count = k;
+    return MTPT_OK;
+}
+
+}  // extern "C"
+
+// ==================================================================== serving
+// A pool keeps independent simulations resident and advances all active ones
+// together.  One tick enqueues, for every group of sims sharing (dim,
+// precision, species, moving, row sums needed), one launch per phase that
+// covers all sims of the group: block b of a launch finds its sim by binary
+// search in a prefix of blocks per sim.  The per-tick argument arrays travel
+// through a ring of pinned host buffers and device buffers; a ring slot is
+// reused only after the event recorded behind its last launch has fired.
+namespace {
+
+struct RingSlot {
+    void* host = nullptr;    // pinned
+    void* dev = nullptr;
+    size_t cap = 0;
+    hipEvent_t ev = nullptr;
+    bool armed = false;
+};
+
+}  // namespace
+
+struct mtpt_pool {
+    size_t budget = 0;
+    size_t held = 0;
+    int32_t max_slots = 1;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    Alloc alloc;
+    std::map<int64_t, mtpt_sim*> sims;   // ticket -> sim, ordered by admission
+    std::map<int64_t, size_t> bytes_of;
+    int64_t next_ticket = 1;
+    RingSlot ring[4];
+    int64_t ticks = 0;
+};
+
+namespace {
+
+int ring_reserve(mtpt_pool* p, RingSlot& r, size_t bytes)
+{
+    if (r.armed) {
+        HIP_TRY(hipEventSynchronize(r.ev));
+        r.armed = false;
+    }
+    if (!r.ev)
+        HIP_TRY(hipEventCreateWithFlags(&r.ev, hipEventDisableTiming));
+    if (r.cap >= bytes)
+        return MTPT_OK;
+    if (r.host)
+        (void)hipHostFree(r.host);
+    p->alloc.put(r.dev);
+    r.host = nullptr;
+    r.dev = nullptr;
+    r.cap = 0;
+    const size_t cap = align_up(std::max<size_t>(bytes, 65536), 4096);
+    HIP_TRY(hipHostMalloc(&r.host, cap, hipHostMallocDefault));
+    r.dev = p->alloc.get(cap);
+    if (!r.dev)
+        return fail(MTPT_E_NOMEM, "pool argument buffer allocation failed");
+    r.cap = cap;
+    return MTPT_OK;
+}
+
+struct GroupKey {
+    int dim, prec, ns, moving, rowsum;
+    bool operator<(const GroupKey& o) const
+    {
+        if (dim != o.dim) return dim < o.dim;
+        if (prec != o.prec) return prec < o.prec;
+        if (ns != o.ns) return ns < o.ns;
+        if (moving != o.moving) return moving < o.moving;
+        return rowsum < o.rowsum;
+    }
+};
+
+}  // namespace
+
+extern "C" {
+
+int mtpt_pool_create(size_t hbm_budget, int32_t max_slots, void* hip_stream, const mtpt_allocator* alloc,
+                     mtpt_pool** out)
+{
+    if (!out)
+        return fail(MTPT_E_ARG, "out is NULL");
+    *out = nullptr;
+    if (max_slots < 1)
+        return fail(MTPT_E_ARG, "max_slots must be >= 1");
+    if (alloc && (!alloc->alloc || !alloc->free))
+        return fail(MTPT_E_ARG, "allocator needs both alloc and free");
+    mtpt_pool* p = new mtpt_pool();
+    p->max_slots = max_slots;
+    if (alloc) {
+        p->alloc.a = *alloc;
+        p->alloc.custom = true;
+    }
+    if (hbm_budget == 0) {
+        size_t fr = 0, tot = 0;
+        if (hipMemGetInfo(&fr, &tot) != hipSuccess) {
+            delete p;
+            return fail(MTPT_E_DEVICE, "hipMemGetInfo failed");
+        }
+        hbm_budget = fr / 10 * 9;
+    }
+    p->budget = hbm_budget;
+    if (hip_stream) {
+        p->stream = static_cast<hipStream_t>(hip_stream);
+    } else {
+        if (hipStreamCreateWithFlags(&p->stream, hipStreamNonBlocking) != hipSuccess) {
+            delete p;
+            return fail(MTPT_E_DEVICE, "hipStreamCreateWithFlags failed");
+        }
+        p->own_stream = true;
+    }
+    *out = p;
+    return MTPT_OK;
+}
+
+int mtpt_pool_admit(mtpt_pool* p, const mtpt_params* params, const double* pos, const double* mass,
+                    int64_t n_steps, int64_t* ticket)
+{
+    if (!p || !ticket)
+        return fail(MTPT_E_ARG, "NULL argument");
+    if (n_steps < 1)
+        return fail(MTPT_E_ARG, "n_steps must be >= 1");
+    int rc = validate(params);
+    if (rc)
+        return rc;
+    const Plan q = make_plan(*params);
+    // the result export stages n*S doubles next to the sim
+    const size_t need = q.bytes + static_cast<size_t>(q.n) * q.ns * 8;
+    if (static_cast<int32_t>(p->sims.size()) >= p->max_slots)
+        return fail(MTPT_E_NOMEM, "no free slot (%d active)", static_cast<int>(p->sims.size()));
+    if (p->held + need > p->budget)
+        return fail(MTPT_E_NOMEM, "budget: %zu held + %zu needed > %zu", p->held, need, p->budget);
+    mtpt_sim* s = nullptr;
+    rc = new_sim(params, pos, mass, p->stream, p->alloc.custom ? &p->alloc.a : nullptr, &s);
+    if (rc)
+        return rc;
+    s->steps_target = n_steps;
+    const int64_t t = p->next_ticket++;
+    p->sims[t] = s;
+    p->bytes_of[t] = need;
+    p->held += need;
+    *ticket = t;
+    return MTPT_OK;
+}
+
+int mtpt_pool_tick(mtpt_pool* p, int32_t* n_completed)
+{
+    if (!p)
+        return fail(MTPT_E_ARG, "pool is NULL");
+    std::map<GroupKey, std::vector<mtpt_sim*>> groups;
+    for (auto& kv : p->sims) {
+        mtpt_sim* s = kv.second;
+        if (s->steps_done >= s->steps_target || s->q.n == 0)
+            continue;
+        const GroupKey k{s->q.dim, s->q.prec, s->q.ns, s->moving ? 1 : 0, (s->moving || !s->s_valid) ? 1 : 0};
+        groups[k].push_back(s);
+    }
+    // layout of the argument block: per group, SimArgs[ns] then PH_COUNT
+    // prefixes of (ns + 1) u32
+    size_t bytes = 0;
+    std::vector<size_t> goff;
+    for (auto& g : groups) {
+        goff.push_back(bytes);
+        const size_t ns = g.second.size();
+        bytes = align_up(bytes + ns * sizeof(SimArgs), 256);
+        bytes = align_up(bytes + PH_COUNT * (ns + 1) * sizeof(uint32_t), 256);
+    }
+    int32_t completed = 0;
+    if (!groups.empty()) {
+        RingSlot& r = p->ring[p->ticks % 4];
+        int rc = ring_reserve(p, r, bytes);
+        if (rc)
+            return rc;
+        char* h = static_cast<char*>(r.host);
+        size_t gi = 0;
+        for (auto& g : groups) {
+            const size_t ns = g.second.size();
+            SimArgs* args = reinterpret_cast<SimArgs*>(h + goff[gi]);
+            uint32_t* pre = reinterpret_cast<uint32_t*>(h + align_up(goff[gi] + ns * sizeof(SimArgs), 256));
+            for (size_t i = 0; i < ns; ++i) {
+                bool need = false;
+                args[i] = step_args(g.second[i], &need);
+            }
+            for (int ph = 0; ph < PH_COUNT; ++ph) {
+                uint32_t* o = pre + ph * (ns + 1);
+                o[0] = 0;
+                for (size_t i = 0; i < ns; ++i)
+                    o[i + 1] = o[i] + phase_blocks(ph, args[i]);
+            }
+            ++gi;
+        }
+        HIP_TRY(hipMemcpyAsync(r.dev, r.host, bytes, hipMemcpyHostToDevice, p->stream));
+        gi = 0;
+        for (auto& g : groups) {
+            const GroupKey& k = g.first;
+            const size_t ns = g.second.size();
+            char* d = static_cast<char*>(r.dev);
+            const SimArgs* dargs = reinterpret_cast<const SimArgs*>(d + goff[gi]);
+            const uint32_t* dpre = reinterpret_cast<const uint32_t*>(d + align_up(goff[gi] + ns * sizeof(SimArgs), 256));
+            const uint32_t* hpre = reinterpret_cast<const uint32_t*>(h + align_up(goff[gi] + ns * sizeof(SimArgs), 256));
+            std::vector<int> phases;
+            if (k.moving)
+                phases = {PH_BIN, PH_SCAN_REDUCE, PH_SCAN_TOP, PH_SCAN_DOWN, PH_SCATTER, PH_CELLSORT, PH_GATHER};
+            if (k.rowsum)
+                phases.push_back(PH_ROWSUM);
+            phases.push_back(PH_TRANSFER);
+            for (int ph : phases) {
+                Batch b;
+                b.args = dargs;
+                b.blk_off = dpre + ph * (ns + 1);
+                b.nsims = static_cast<int32_t>(ns);
+                b.total_blocks = hpre[ph * (ns + 1) + ns];
+                HIP_TRY(launch_phase_batched(ph, k.dim, k.prec, k.ns, b, p->stream));
+            }
+            for (mtpt_sim* s : g.second) {
+                s->steps_done += 1;
+                if (!s->moving)
+                    s->s_valid = true;
+                if (s->steps_done == s->steps_target)
+                    ++completed;
+            }
+            ++gi;
+        }
+        HIP_TRY(hipEventRecord(r.ev, p->stream));
+        r.armed = true;
+        p->ticks += 1;
+    }
+    if (n_completed)
+        *n_completed = completed;
+    return MTPT_OK;
+}
+
+int mtpt_pool_done(mtpt_pool* p, int64_t ticket, int32_t* done)
+{
+    if (!p || !done)
+        return fail(MTPT_E_ARG, "NULL argument");
+    auto it = p->sims.find(ticket);
+    if (it == p->sims.end())
+        return fail(MTPT_E_ARG, "unknown ticket %lld", (long long)ticket);
+    mtpt_sim* s = it->second;
+    *done = 0;
+    if (s->steps_done >= s->steps_target) {
+        HIP_TRY(hipStreamSynchronize(p->stream));
+        *done = 1;
+    }
+    return MTPT_OK;
+}
+
+int mtpt_pool_result(mtpt_pool* p, int64_t ticket, double* mass_out)
+{
+    if (!p)
+        return fail(MTPT_E_ARG, "pool is NULL");
+    auto it = p->sims.find(ticket);
+    if (it == p->sims.end())
+        return fail(MTPT_E_ARG, "unknown ticket %lld", (long long)ticket);
+    mtpt_sim* s = it->second;
+    if (s->steps_done < s->steps_target)
+        return fail(MTPT_E_STATE, "ticket %lld has %lld of %lld steps", (long long)ticket,
+                    (long long)s->steps_done, (long long)s->steps_target);
+    const int rc = mtpt_masses(s, mass_out);
+    if (rc && rc != MTPT_E_NONFINITE)
+        return rc;
+    (void)hipStreamSynchronize(p->stream);
+    release(s);
+    p->held -= p->bytes_of[ticket];
+    p->bytes_of.erase(ticket);
+    p->sims.erase(it);
+    return rc;
+}
+
+int mtpt_pool_usage(mtpt_pool* p, int32_t* active, size_t* bytes_held, size_t* budget)
+{
+    if (!p)
+        return fail(MTPT_E_ARG, "pool is NULL");
+    if (active)
+        *active = static_cast<int32_t>(p->sims.size());
+    if (bytes_held)
+        *bytes_held = p->held;
+    if (budget)
+        *budget = p->budget;
+    return MTPT_OK;
+}
+
+int mtpt_pool_destroy(mtpt_pool* p)
+{
+    if (!p)
+        return MTPT_OK;
+    (void)hipStreamSynchronize(p->stream);
+    for (auto& kv : p->sims)
+        release(kv.second);
+    p->sims.clear();
+    for (auto& r : p->ring) {
+        if (r.host)
+            (void)hipHostFree(r.host);
+        p->alloc.put(r.dev);
+        if (r.ev)
+            (void)hipEventDestroy(r.ev);
+    }
+    if (p->own_stream && p->stream)
+        (void)hipStreamDestroy(p->stream);
+    delete p;
+    return MTPT_OK;
+}
+
+}  // extern "C"

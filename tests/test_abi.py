@@ -1,0 +1,106 @@
+"""Host-side checks of the C-ABI library (no GPU needed).
+
+* libmtpt.so loads and exports every function include/mtpt.h declares.
+* Parameter validation rejects bad input before any device call.
+* The buffer plan sizes what the kernels index.
+"""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2204_03756_amd import build as lib_build
+from paper_2204_03756_amd import mtpt
+from paper_2204_03756_amd import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if lib_build.stale():
+        lib_build.build()
+    return mtpt.load()
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "mtpt.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(mtpt_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_exports_every_declared_symbol(lib):
+    names = declared_functions()
+    assert len(names) >= 19
+    raw = C.CDLL(mtpt.lib_path())
+    missing = [n for n in names if not hasattr(raw, n)]
+    assert not missing, missing
+    assert lib.mtpt_abi_version() == mtpt.MTPT_ABI_VERSION
+
+
+def test_params_struct_matches_header():
+    text = open(os.path.join(ROOT, "include", "mtpt.h")).read()
+    body = text[text.index("typedef struct {\n    uint32_t abi_version"):text.index("} mtpt_params;")]
+    body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
+    fields = re.findall(r"\b(\w+)(?:\[3\])?[,;]", body)
+    names = [f for f, _ in mtpt.mtpt_params._fields_]
+    assert [f for f in fields if f in names] == names
+
+
+def _call_create(lib, p, x, m):
+    h = C.c_void_p()
+    f64 = C.POINTER(C.c_double)
+    rc = lib.mtpt_create(C.byref(p), x.ctypes.data_as(f64), m.ctypes.data_as(f64), None, None,
+                         C.byref(h))
+    return rc, h
+
+
+def test_validation_rejects_bad_params(lib):
+    w = W.plain2d(n=100)
+    x = np.ascontiguousarray(w.x0)
+    m = np.ascontiguousarray(w.m0)
+    cases = []
+    p = mtpt.make_params(w.params); p.abi_version = 99; cases.append((p, mtpt.MTPT_E_ABI))
+    p = mtpt.make_params(w.params); p.dim = 4; cases.append((p, mtpt.MTPT_E_ARG))
+    p = mtpt.make_params(w.params); p.n = -1; cases.append((p, mtpt.MTPT_E_ARG))
+    p = mtpt.make_params(w.params); p.n_species = 2; cases.append((p, mtpt.MTPT_E_ARG))
+    p = mtpt.make_params(w.params); p.precision = 5; cases.append((p, mtpt.MTPT_E_ARG))
+    p = mtpt.make_params(w.params); p.dt = 0.0; cases.append((p, mtpt.MTPT_E_ARG))
+    p = mtpt.make_params(w.params); p.d_mt = -1.0; cases.append((p, mtpt.MTPT_E_ARG))
+    p = mtpt.make_params(w.params); p.d_rw = float("nan"); cases.append((p, mtpt.MTPT_E_ARG))
+    p = mtpt.make_params(w.params); p.beta = 1.5; cases.append((p, mtpt.MTPT_E_ARG))
+    p = mtpt.make_params(w.params); p.hi[1] = p.lo[1]; cases.append((p, mtpt.MTPT_E_ARG))
+    p = mtpt.make_params(w.params); p.start_step = -3; cases.append((p, mtpt.MTPT_E_ARG))
+    for p, code in cases:
+        rc, h = _call_create(lib, p, x, m)
+        assert rc == code and not h.value
+        assert lib.mtpt_last_error().decode()
+    # a position outside the box
+    xb = x.copy(); xb[7, 1] = w.params.hi[1] + 1e-9
+    rc, h = _call_create(lib, mtpt.make_params(w.params), xb, m)
+    assert rc == mtpt.MTPT_E_ARG and b"outside" in lib.mtpt_last_error()
+    mb = m.copy(); mb[0, 3] = np.inf
+    rc, h = _call_create(lib, mtpt.make_params(w.params), x, mb)
+    assert rc == mtpt.MTPT_E_ARG
+
+
+def test_null_handles_are_errors_or_noops(lib):
+    assert lib.mtpt_destroy(None) == 0
+    assert lib.mtpt_pool_destroy(None) == 0
+    assert lib.mtpt_step(None, 1) == mtpt.MTPT_E_ARG
+    assert lib.mtpt_masses(None, None) == mtpt.MTPT_E_ARG
+
+
+def test_plan_bytes_scale_with_n(lib):
+    small = mtpt.mtpt_sim_bytes(W.rw2d(n=40_000).params)
+    big = W.rw2d(n=400_000).params
+    big_b = mtpt.mtpt_sim_bytes(big)
+    # FP32 positions, FP64 masses: ~5 position arrays, 2 mass arrays, 6 u32
+    # arrays and ~2 u32 per cell per particle
+    per = big_b / big.n
+    assert 40 < per < 120
+    assert big_b > 8 * small
+    p64 = W.with_precision(W.rw2d(n=400_000), W.FP64).params
+    assert mtpt.mtpt_sim_bytes(p64) > big_b

@@ -1,0 +1,94 @@
+"""Serving pool on the GPU: continuous batching of independent sims.
+
+* Every result out of the pool equals the same sim run alone, bit for bit,
+  and the oracle within the FP32 bar.
+* Requests arriving while others run are admitted as slots and budget free
+  up; admission beyond the budget or the slots is refused (retry later).
+"""
+import numpy as np
+import pytest
+
+from paper_2204_03756_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def mt():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+    from paper_2204_03756_amd import mtpt
+    mtpt.load()
+    return mtpt
+
+
+def alone(mt, r):
+    with mt.Sim(r.params, r.x0, r.m0, allocator=mt.TorchAllocator()) as sim:
+        sim.step(r.steps)
+        return sim.masses()
+
+
+def test_pool_alone_equals_mix(mt, oracle):
+    reqs = [W.request(i, n_min=2e3, n_max=3e4) for i in range(10)]
+    for r in reqs:
+        r.steps = min(r.steps, 25)
+    pool = mt.mtpt_pool_create(0, 4)
+    try:
+        pending = list(reqs)
+        active = {}
+        results = {}
+        ticks = 0
+        while pending or active:
+            # admit while slots free up (continuous batching)
+            while pending:
+                r = pending[0]
+                t = mt.mtpt_pool_admit(pool, r.params, r.x0, r.m0, r.steps)
+                if t is None:
+                    break
+                active[t] = r
+                pending.pop(0)
+            assert len(active) <= 4
+            mt.mtpt_pool_tick(pool)
+            ticks += 1
+            for t in list(active):
+                if mt.mtpt_pool_done(pool, t):
+                    r = active.pop(t)
+                    results[r.rid] = mt.mtpt_pool_result(pool, t, r.params.n, 1)
+        print(f"  pool: {len(reqs)} sims in {ticks} ticks", flush=True)
+    finally:
+        mt.mtpt_pool_destroy(pool)
+    for r in reqs:
+        a = alone(mt, r)
+        assert np.array_equal(a, results[r.rid]), f"request {r.rid} differs alone vs in the mix"
+    for r in reqs[:4]:
+        ref = oracle.run(r.params, r.x0, r.m0, r.steps)
+        err = np.max(np.abs(results[r.rid] - ref.m)) / np.max(np.abs(ref.m))
+        assert err <= 1e-5
+
+
+def test_pool_admission_budget_and_slots(mt):
+    r = W.request(3, n_min=5e3, n_max=6e3)
+    need = mt.mtpt_sim_bytes(r.params)
+    pool = mt.mtpt_pool_create(int(need * 1.5 + r.params.n * 8), 8)
+    try:
+        t1 = mt.mtpt_pool_admit(pool, r.params, r.x0, r.m0, 3)
+        assert t1 is not None
+        assert mt.mtpt_pool_admit(pool, r.params, r.x0, r.m0, 3) is None   # over budget
+        active, held, budget = mt.mtpt_pool_usage(pool)
+        assert active == 1 and held <= budget
+        with pytest.raises(mt.MtptError):
+            mt.mtpt_pool_result(pool, t1, r.params.n, 1)                   # not finished
+        while not mt.mtpt_pool_done(pool, t1):
+            mt.mtpt_pool_tick(pool)
+        mt.mtpt_pool_result(pool, t1, r.params.n, 1)
+        assert mt.mtpt_pool_admit(pool, r.params, r.x0, r.m0, 3) is not None
+    finally:
+        mt.mtpt_pool_destroy(pool)
+    pool = mt.mtpt_pool_create(0, 1)
+    try:
+        assert mt.mtpt_pool_admit(pool, r.params, r.x0, r.m0, 2) is not None
+        assert mt.mtpt_pool_admit(pool, r.params, r.x0, r.m0, 2) is None   # no slot
+    finally:
+        mt.mtpt_pool_destroy(pool)
