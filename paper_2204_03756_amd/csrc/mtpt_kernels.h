@@ -3,17 +3,19 @@
 //
 // Layout in HBM (per simulation, n particles, S species, T = double in FP64
 // mode and float otherwise, M = float in Kahan mode and double otherwise):
-//   X[k][n]     T    positions, structure of arrays, sorted by cell and then
-//                    by pid inside a cell (the order every MT pass walks)
+//   X[k][n]     T    positions, structure of arrays, sorted by cell (cells
+//                    numbered x fastest) and inside a cell by (x, pid), so
+//                    every row of cells is one x-sorted run of the arrays
 //   XT[k][n]    T    walked positions in the order before re-binning
 //   M[2][S][n]  M    masses, two buffers (Jacobi update)
 //   P[2][n]     u32  pid of each sorted slot, two buffers
 //   Srow[n]     T    row sums s_i = sum_j K_ij
 //   cell, rank, perm [n] u32   binning scratch
-//   counts[ncells padded], starts[ncells+1] u32   cell histogram and offsets
-//   bsum[]      u32  per-block partial sums of the scan
-//   partials[]  f64  per-block mass partial sums
-//   DevStats         pair counters, totals, completion ticket
+//   counts[], starts[] u32     cell histogram and offsets (tile-padded)
+//   bsum[]      u32  per-tile partial sums of the scan
+//   partials[]  f64  per-workgroup mass partial sums [parts][S]
+//   pair_part[] u32  per-workgroup pair counts
+//   DevStats         counters and totals
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -21,19 +23,21 @@
 
 namespace mtpt {
 
-constexpr int kBlock = 256;          // threads per block, 4 wave64s
+constexpr int kBlock = 256;          // threads per workgroup, 4 wave64s
 constexpr int kScanItems = 16;       // counts per thread in the scan
 constexpr int kScanTile = kBlock * kScanItems;
+constexpr int kFinalBlock = 1024;    // threads of the finalize kernel
+constexpr int kMaxTileRows = 64;     // tile extent in y, cells
+constexpr int kMaxSegs = 3 * (kMaxTileRows + 2);
 
 struct DevStats {
-    unsigned long long pairs_acc;    // pairs counted by the current row-sum pass
     unsigned long long pairs_last;   // pairs of the last step
     unsigned long long pairs_total;  // over all steps
-    unsigned int blocks_done;        // completion ticket of the transfer pass
     int nonfinite;                   // sticky: a total was NaN or infinite
+    int pad0;
     double totals[3];                // mass totals after the last step
     long long steps;                 // steps completed on the device
-    double pad[2];
+    double pad[3];
 };
 
 // Everything one launch of one phase needs about one simulation.  Pointers
@@ -47,6 +51,9 @@ struct SimArgs {
     double inv_side[3];
     int32_t nc[3];
     uint32_t ncells;
+    // tiles of the mass-transfer passes: tx * ty cells of one z plane
+    int32_t tile[2];
+    uint32_t tiles_x, tiles_y, ntiles;
     // box and walk
     double lo[3], hi[3];
     float lof[3], hif[3];
@@ -54,13 +61,15 @@ struct SimArgs {
     uint64_t seed;
     int64_t step;
     // weights: K = exp(-kc r^2), kc = beta / (4 D_MT dt)
+    double psi;
     double psi2;             // psi * psi (FP64, the canonical cutoff)
+    double win;              // x-window half width, psi (1 + 1e-6)
     float psi2_in;           // FP32 r^2 below this: inside for sure
     float psi2_out;          // FP32 r^2 above this: outside for sure
     double kc;
     float kcf;
-    double beta;
     float betaf;
+    double beta;
     double k_react, to_c, to_m, dt;
     // buffers
     void* x[3];
@@ -69,7 +78,7 @@ struct SimArgs {
     void* m_mid[3];          // masses in the current sorted order
     void* m_dst[3];          // transfer output
     uint32_t* pid_src;
-    uint32_t* pid_dst;       // gather output = current sorted pids
+    uint32_t* pid_dst;       // place output = current sorted pids
     void* srow;
     uint32_t* cell;
     uint32_t* rank;
@@ -78,47 +87,50 @@ struct SimArgs {
     uint32_t* starts;
     uint32_t* bsum;
     double* partials;
+    uint32_t* pair_part;
     DevStats* st;
-    uint32_t scan_blocks;    // ceil(ncells / kScanTile)
+    uint32_t scan_blocks;    // ceil((ncells + 1) / kScanTile)
     uint32_t part_blocks;    // ceil(n / kBlock)
     int32_t recompute_s;     // the row-sum pass ran this step
     int32_t walk;            // apply the jump in the bin pass (0 at create)
 };
 
-// Launch helpers (host).  prec: 0 FP64, 1 FP32W_FP64ACC, 2 FP32_KAHAN.
-// Single-sim launches take the arguments by value; batched launches take a
-// device array of SimArgs and a device prefix of blocks per sim.
+// Batched launches: a device array of SimArgs and a device prefix of blocks
+// per sim; block b of the launch belongs to the sim whose prefix range holds b.
 struct Batch {
-    const SimArgs* args;       // device array [nsims]
-    const uint32_t* blk_off;   // device [nsims + 1], prefix of blocks
+    const SimArgs* args;
+    const uint32_t* blk_off;   // [nsims + 1]
     int32_t nsims;
     uint32_t total_blocks;
 };
 
 enum Phase {
-    PH_BIN = 0,
-    PH_SCAN_REDUCE,
-    PH_SCAN_TOP,
-    PH_SCAN_DOWN,
-    PH_SCATTER,
-    PH_CELLSORT,
-    PH_GATHER,
-    PH_ROWSUM,
-    PH_TRANSFER,
+    PH_BIN = 0,       // walk + reflect + cell id + histogram
+    PH_SCAN_REDUCE,   // per-tile sums of the histogram
+    PH_SCAN_TOP,      // scan of the tile sums
+    PH_SCAN_DOWN,     // cell offsets, histogram cleared
+    PH_SCATTER,       // slot of every particle inside its cell
+    PH_PLACE,         // rank inside the cell by (x, pid); gather into place
+    PH_ROWSUM,        // s_i
+    PH_TRANSFER,      // exchange (+ reaction), per-workgroup mass sums
+    PH_FINALIZE,      // totals, pair counters
     PH_COUNT
 };
 
 const char* phase_name(int ph);
+
+// particles of positions staged per workgroup in the tiled passes
+int tile_capacity(int dim, int prec);
 
 // blocks a phase needs for one sim
 uint32_t phase_blocks(int ph, const SimArgs& a);
 
 // single-sim launch of a phase
 hipError_t launch_phase(int ph, int dim, int prec, const SimArgs& a, hipStream_t s);
-// batched launch of a phase over sims that share (dim, prec)
+// batched launch of a phase over sims that share (dim, prec, ns)
 hipError_t launch_phase_batched(int ph, int dim, int prec, int ns, const Batch& b, hipStream_t s);
 
-// exports
+// exports and set-up
 hipError_t launch_unpermute_mass(int prec, const SimArgs& a, const void* const* m_cur,
                                  const uint32_t* pid_cur, double* out, hipStream_t s);
 hipError_t launch_unpermute_pos(int dim, int prec, const SimArgs& a, const uint32_t* pid_cur,
@@ -128,7 +140,7 @@ hipError_t launch_nb_count(int dim, int prec, const SimArgs& a, const uint32_t* 
                            uint32_t* rowcnt, hipStream_t s);
 hipError_t launch_nb_fill(int dim, int prec, const SimArgs& a, const uint32_t* pid_cur,
                           const int64_t* row_ptr, int64_t* col, hipStream_t s);
-hipError_t launch_scan_u32_to_i64(const uint32_t* in, int64_t* out, int64_t len, uint32_t* tmp_counts,
+hipError_t launch_scan_u32_to_i64(const uint32_t* in, int64_t* out, int64_t len, uint32_t* tmp,
                                   uint32_t* bsum, hipStream_t s);
 
 }  // namespace mtpt

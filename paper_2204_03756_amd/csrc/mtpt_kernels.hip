@@ -5,18 +5,21 @@
 //              walls), cell id of the walked position, cell histogram
 //   scan       exclusive scan of the histogram -> cell offsets
 //   scatter    slot of every particle inside its cell
-//   cellsort   order inside every cell by pid (makes the layout, and with it
-//              every floating-point sum, independent of atomic order)
-//   gather     positions, masses and pids into the new sorted order
-//   rowsum     s_i = sum_j K_ij over the 3^d neighbouring cells, K_ii = 1 included
-//              (Eq. (2)-(3) without the prefactor, which cancels in W)
+//   place      rank inside the cell by (x, pid), gather positions, masses and
+//              pids into that slot: the layout, and with it every
+//              floating-point sum, does not depend on the order of atomics
+//   rowsum     s_i = sum_j K_ij, K_ii = 1 included (Eq. (2)-(3) without the
+//              prefactor, which cancels in W)
 //   transfer   W_ij = 2 K_ij / (s_i + s_j), M_i' = M_i + beta sum_j W_ij (M_j - M_i)
-//              (Eq. (4)-(5)), optional A+B->C epilogue, per-block mass sums and
-//              the final FP64 totals in the last block to finish
-// The K-D tree of the paper is replaced by the cell list: with cell side >=
-// psi every neighbour within psi lies in the 3^d cells around a particle, and
-// since cells are numbered x-fastest, the three cells of one (y, z) row are
-// one contiguous range of the sorted arrays.
+//              (Eq. (4)-(5)), optional A+B->C epilogue, per-workgroup mass sums
+//   finalize   FP64 totals and pair counters, summed in a fixed order
+// The K-D tree search of the paper is replaced by the cell list (cell side
+// >= psi).  The two mass-transfer passes run per tile of tx * ty cells of one
+// z plane: the workgroup stages the positions (and row sums) of every cell
+// row of the tile and its one-cell halo in LDS -- each such row is one
+// contiguous, x-sorted run of the sorted arrays -- and every particle scans,
+// in each of its 3^(d-1) neighbouring rows, only the x-window |x_j - x_i| <= psi
+// found by binary search.
 #include "mtpt_kernels.h"
 #include "mtpt_rng.h"
 
@@ -29,6 +32,11 @@ template <int PREC> struct Types;
 template <> struct Types<0> { using T = double; using M = double; using A = double; };
 template <> struct Types<1> { using T = float;  using M = double; using A = double; };
 template <> struct Types<2> { using T = float;  using M = float;  using A = float;  };
+
+// positions staged per workgroup (tile cells plus halo)
+template <int D, typename T> struct TileCap {
+    static constexpr int value = D == 2 ? 1024 : (sizeof(T) == 8 ? 1536 : 2560);
+};
 
 __device__ __forceinline__ int cell_coord(double x, double glo, double inv, int nc)
 {
@@ -52,10 +60,10 @@ __device__ __forceinline__ double r2_canonical(const double* xi, const double* x
     return r2;
 }
 
-// Inside test and squared distance for the arithmetic of the path.  FP64:
-// the canonical r^2 against psi^2.  FP32: the FP32 r^2 decides outside a
-// 1e-5 relative band around psi^2; inside it the canonical FP64 r^2 of the
-// same FP32 positions decides (FP32 r^2 error is below 1e-6 relative).
+// Inside test and kernel value in the arithmetic of the path.  FP64: the
+// canonical r^2 against psi^2.  FP32: the FP32 r^2 decides outside a 1e-5
+// relative band around psi^2 (its error is below 1e-6 relative); inside the
+// band the canonical FP64 r^2 of the same FP32 positions decides.
 template <int D, typename T> struct Pair;
 
 template <int D> struct Pair<D, double> {
@@ -66,9 +74,10 @@ template <int D> struct Pair<D, double> {
         *r2o = r2;
         return r2 <= a.psi2;
     }
-    __device__ __forceinline__ static double kernel(const SimArgs& a, double r2)
+    __device__ __forceinline__ static double kernel(const SimArgs& a, double r2) { return exp(-a.kc * r2); }
+    __device__ __forceinline__ static double weight(double k, double si, double sj)
     {
-        return exp(-a.kc * r2);
+        return (k + k) / (si + sj);
     }
 };
 
@@ -96,9 +105,10 @@ template <int D> struct Pair<D, float> {
         }
         return r2_canonical<D>(pi, pj) <= a.psi2;
     }
-    __device__ __forceinline__ static float kernel(const SimArgs& a, float r2)
+    __device__ __forceinline__ static float kernel(const SimArgs& a, float r2) { return __expf(-a.kcf * r2); }
+    __device__ __forceinline__ static float weight(float k, float si, float sj)
     {
-        return __expf(-a.kcf * r2);
+        return (k + k) * __builtin_amdgcn_rcpf(si + sj);
     }
 };
 
@@ -131,7 +141,49 @@ __device__ __forceinline__ float walk_reflect<float>(float x, double z, double s
     return v;
 }
 
-// wave64 inclusive scan and block (4 waves) exclusive scan
+// x-window [x_i - win, x_i + win] in the type of the positions, rounded
+// outward so that no x within the exact window falls outside it
+template <typename T> struct Window;
+template <> struct Window<double> {
+    __device__ __forceinline__ static void make(double xi, double win, double* lo, double* hi)
+    {
+        *lo = xi - win;
+        *hi = xi + win;
+    }
+};
+// next float below / above a finite v
+__device__ __forceinline__ float float_down(float v)
+{
+    const uint32_t b = __float_as_uint(v);
+    if (v == 0.0f)
+        return __uint_as_float(0x80000001u);
+    return __uint_as_float(v > 0.0f ? b - 1u : b + 1u);
+}
+__device__ __forceinline__ float float_up(float v)
+{
+    const uint32_t b = __float_as_uint(v);
+    if (v == 0.0f)
+        return __uint_as_float(0x00000001u);
+    return __uint_as_float(v > 0.0f ? b + 1u : b - 1u);
+}
+
+template <> struct Window<float> {
+    __device__ __forceinline__ static void make(float xi, double win, float* lo, float* hi)
+    {
+        const double l = static_cast<double>(xi) - win;
+        const double h = static_cast<double>(xi) + win;
+        float lf = static_cast<float>(l);
+        float hf = static_cast<float>(h);
+        if (static_cast<double>(lf) > l)
+            lf = float_down(lf);
+        if (static_cast<double>(hf) < h)
+            hf = float_up(hf);
+        *lo = lf;
+        *hi = hf;
+    }
+};
+
+// wave64 inclusive scan and workgroup exclusive scan (kBlock threads)
 __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v)
 {
     const int lane = threadIdx.x & 63;
@@ -164,10 +216,11 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* total)
     return base + inc - v;
 }
 
-template <typename V>
+// workgroup sum in a fixed order; result valid in thread 0
+template <int NT, typename V>
 __device__ __forceinline__ V block_sum(V v)
 {
-    __shared__ V red[kBlock / 64];
+    __shared__ V red[NT / 64];
     const int lane = threadIdx.x & 63;
     const int wid = threadIdx.x >> 6;
 #pragma unroll
@@ -179,14 +232,14 @@ __device__ __forceinline__ V block_sum(V v)
     V t = V(0);
     if (threadIdx.x == 0) {
 #pragma unroll
-        for (int w = 0; w < kBlock / 64; ++w)
+        for (int w = 0; w < NT / 64; ++w)
             t += red[w];
     }
     __syncthreads();
-    return t;  // valid in thread 0
+    return t;
 }
 
-// -------------------------------------------------------------- phase bodies
+// -------------------------------------------------------------- binning
 template <int D, typename T>
 __device__ __forceinline__ void bin_body(const SimArgs& a, uint32_t blk)
 {
@@ -228,7 +281,7 @@ __device__ __forceinline__ void scan_reduce_body(const uint32_t* in, uint32_t* b
         const uint4 w = p[q];
         s += w.x + w.y + w.z + w.w;
     }
-    const uint32_t t = block_sum<uint32_t>(s);
+    const uint32_t t = block_sum<kBlock, uint32_t>(s);
     if (threadIdx.x == 0)
         bsum[blk] = t;
 }
@@ -286,101 +339,38 @@ __device__ __forceinline__ void scatter_body(const SimArgs& a, uint32_t blk)
     a.perm[a.starts[a.cell[i]] + a.rank[i]] = static_cast<uint32_t>(i);
 }
 
-__device__ __forceinline__ void cellsort_body(const SimArgs& a, uint32_t blk)
-{
-    const int64_t c = static_cast<int64_t>(blk) * kBlock + threadIdx.x;
-    if (c >= a.ncells)
-        return;
-    const uint32_t b = a.starts[c], e = a.starts[c + 1];
-    for (uint32_t k = b + 1; k < e; ++k) {
-        const uint32_t v = a.perm[k];
-        const uint32_t key = a.pid_src[v];
-        uint32_t j = k;
-        while (j > b) {
-            const uint32_t u = a.perm[j - 1];
-            if (a.pid_src[u] <= key)
-                break;
-            a.perm[j] = u;
-            --j;
-        }
-        a.perm[j] = v;
-    }
-}
-
+// Slot k holds particle src after the scatter, in arbitrary order inside its
+// cell.  Its final slot is the cell start plus the number of cell members
+// with a smaller (x, pid) key.
 template <int D, typename T, typename M>
-__device__ __forceinline__ void gather_body(const SimArgs& a, uint32_t blk)
+__device__ __forceinline__ void place_body(const SimArgs& a, uint32_t blk)
 {
     const int64_t k = static_cast<int64_t>(blk) * kBlock + threadIdx.x;
     if (k >= a.n)
         return;
+    const T* xt0 = static_cast<const T*>(a.xt[0]);
     const uint32_t src = a.perm[k];
+    const uint32_t c = a.cell[src];
+    const uint32_t b = a.starts[c], e = a.starts[c + 1];
+    const T kx = xt0[src];
+    const uint32_t kp = a.pid_src[src];
+    uint32_t rank = 0;
+    for (uint32_t q = b; q < e; ++q) {
+        const uint32_t o = a.perm[q];
+        const T ox = xt0[o];
+        const uint32_t op = a.pid_src[o];
+        rank += (ox < kx || (ox == kx && op < kp)) ? 1u : 0u;
+    }
+    const uint32_t dst = b + rank;
 #pragma unroll
     for (int d = 0; d < D; ++d)
-        static_cast<T*>(a.x[d])[k] = static_cast<const T*>(a.xt[d])[src];
-    for (int c = 0; c < a.ns; ++c)
-        static_cast<M*>(a.m_mid[c])[k] = static_cast<const M*>(a.m_src[c])[src];
-    a.pid_dst[k] = a.pid_src[src];
+        static_cast<T*>(a.x[d])[dst] = static_cast<const T*>(a.xt[d])[src];
+    for (int s = 0; s < a.ns; ++s)
+        static_cast<M*>(a.m_mid[s])[dst] = static_cast<const M*>(a.m_src[s])[src];
+    a.pid_dst[dst] = kp;
 }
 
-// The neighbour rows of particle i: for each (dy, dz), the contiguous slot
-// range of cells cx-1 .. cx+1 of that row.  f(j) is called for every
-// candidate slot in a fixed order (z, then y, then slot).
-template <int D, typename T, typename F>
-__device__ __forceinline__ void for_candidates(const SimArgs& a, const T* xi, F&& f)
-{
-    int cc[3];
-#pragma unroll
-    for (int k = 0; k < D; ++k)
-        cc[k] = cell_coord(static_cast<double>(xi[k]), a.glo[k], a.inv_side[k], a.nc[k]);
-    const int x0 = cc[0] > 0 ? cc[0] - 1 : 0;
-    const int x1 = cc[0] < a.nc[0] - 1 ? cc[0] + 1 : a.nc[0] - 1;
-    const int zlo = (D == 3) ? (cc[2] > 0 ? cc[2] - 1 : 0) : 0;
-    const int zhi = (D == 3) ? (cc[2] < a.nc[2] - 1 ? cc[2] + 1 : a.nc[2] - 1) : 0;
-    const int ylo = cc[1] > 0 ? cc[1] - 1 : 0;
-    const int yhi = cc[1] < a.nc[1] - 1 ? cc[1] + 1 : a.nc[1] - 1;
-    for (int z = zlo; z <= zhi; ++z) {
-        for (int y = ylo; y <= yhi; ++y) {
-            const uint32_t row = (static_cast<uint32_t>(z) * a.nc[1] + y) * a.nc[0];
-            const uint32_t j0 = a.starts[row + x0];
-            const uint32_t j1 = a.starts[row + x1 + 1];
-            for (uint32_t j = j0; j < j1; ++j)
-                f(j);
-        }
-    }
-}
-
-template <int D, int PREC>
-__device__ __forceinline__ void rowsum_body(const SimArgs& a, uint32_t blk)
-{
-    using T = typename Types<PREC>::T;
-    const int64_t i = static_cast<int64_t>(blk) * kBlock + threadIdx.x;
-    uint32_t pairs = 0;
-    if (i < a.n) {
-        T xi[3];
-#pragma unroll
-        for (int k = 0; k < D; ++k)
-            xi[k] = static_cast<const T*>(a.x[k])[i];
-        T acc = T(0);
-        uint32_t cnt = 0;
-        for_candidates<D, T>(a, xi, [&](uint32_t j) {
-            T xj[3];
-#pragma unroll
-            for (int k = 0; k < D; ++k)
-                xj[k] = static_cast<const T*>(a.x[k])[j];
-            T r2;
-            if (Pair<D, T>::inside(a, xi, xj, &r2)) {
-                acc += Pair<D, T>::kernel(a, r2);
-                ++cnt;
-            }
-        });
-        static_cast<T*>(a.srow)[i] = acc;
-        pairs = cnt - 1u;
-    }
-    const unsigned long long tot = block_sum<unsigned long long>(pairs);
-    if (threadIdx.x == 0 && tot)
-        atomicAdd(&a.st->pairs_acc, tot);
-}
-
+// ------------------------------------------------------------ tiled passes
 // A+B->C inside one particle over dt, exact solution of da/dt = db/dt = -k a b
 // on concentrations (c = N M / V): with D = a - b >= 0,
 // a' = a D / (D - b expm1(-k D dt)), or a/(1 + k a dt) when D = 0; b' = a' - D.
@@ -403,118 +393,300 @@ __device__ __forceinline__ void react3(double* m, const SimArgs& a)
     m[2] = m[2] + reacted * a.to_m;
 }
 
-template <int D, int PREC, int NS>
-__device__ __forceinline__ void transfer_body(const SimArgs& a, uint32_t blk)
+// Per-particle accumulator of the two passes.
+template <int PREC, int NS, bool TRANSFER> struct Acc;
+
+template <int PREC, int NS> struct Acc<PREC, NS, false> {
+    using T = typename Types<PREC>::T;
+    T s = T(0);
+    uint32_t cnt = 0;
+};
+
+template <int PREC, int NS> struct Acc<PREC, NS, true> {
+    using T = typename Types<PREC>::T;
+    using M = typename Types<PREC>::M;
+    using A = typename Types<PREC>::A;
+    T si;
+    M mi[NS];
+    A dl[NS];
+    A comp[NS];
+};
+
+// One candidate j (global slot) with position xj and row sum sj (transfer).
+template <int D, int PREC, int NS, bool TRANSFER>
+__device__ __forceinline__ void visit(const SimArgs& a, const typename Types<PREC>::T* xi,
+                                      const typename Types<PREC>::T* xj, typename Types<PREC>::T sj,
+                                      uint32_t i, uint32_t j, Acc<PREC, NS, TRANSFER>& acc)
 {
     using T = typename Types<PREC>::T;
     using M = typename Types<PREC>::M;
     using A = typename Types<PREC>::A;
-    const int64_t i = static_cast<int64_t>(blk) * kBlock + threadIdx.x;
-    double outv[NS];
-#pragma unroll
-    for (int c = 0; c < NS; ++c)
-        outv[c] = 0.0;
-    if (i < a.n) {
-        T xi[3];
-#pragma unroll
-        for (int k = 0; k < D; ++k)
-            xi[k] = static_cast<const T*>(a.x[k])[i];
-        const T si = static_cast<const T*>(a.srow)[i];
-        M mi[NS];
-        A dl[NS], comp[NS];
-#pragma unroll
-        for (int c = 0; c < NS; ++c) {
-            mi[c] = static_cast<const M*>(a.m_mid[c])[i];
-            dl[c] = A(0);
-            comp[c] = A(0);
-        }
-        const uint32_t self = static_cast<uint32_t>(i);
-        for_candidates<D, T>(a, xi, [&](uint32_t j) {
-            if (j == self)
-                return;
-            T xj[3];
-#pragma unroll
-            for (int k = 0; k < D; ++k)
-                xj[k] = static_cast<const T*>(a.x[k])[j];
-            T r2;
-            if (!Pair<D, T>::inside(a, xi, xj, &r2))
-                return;
-            const T kv = Pair<D, T>::kernel(a, r2);
-            const T sj = static_cast<const T*>(a.srow)[j];
-            const T w = (kv + kv) / (si + sj);
-#pragma unroll
-            for (int c = 0; c < NS; ++c) {
-                const M mj = static_cast<const M*>(a.m_mid[c])[j];
-                if (PREC == 2) {
-                    // Kahan-compensated FP32 accumulation
-                    const A y = static_cast<A>(w) * static_cast<A>(mj - mi[c]) - comp[c];
-                    const A t = dl[c] + y;
-                    comp[c] = (t - dl[c]) - y;
-                    dl[c] = t;
-                } else {
-                    dl[c] += static_cast<A>(w) * static_cast<A>(mj - mi[c]);
-                }
-            }
-        });
-        double mo[3];
+    if (TRANSFER) {
+        if (j == i)
+            return;
+    }
+    T r2;
+    if (!Pair<D, T>::inside(a, xi, xj, &r2))
+        return;
+    const T kv = Pair<D, T>::kernel(a, r2);
+    if constexpr (!TRANSFER) {
+        acc.s += kv;
+        acc.cnt += 1;
+    } else {
+        const T w = Pair<D, T>::weight(kv, acc.si, sj);
 #pragma unroll
         for (int c = 0; c < NS; ++c) {
+            const M mj = static_cast<const M*>(a.m_mid[c])[j];
             if (PREC == 2) {
-                const float nv = mi[c] + a.betaf * dl[c];
-                mo[c] = static_cast<double>(nv);
+                // Kahan-compensated FP32 accumulation
+                const A y = static_cast<A>(w) * static_cast<A>(mj - acc.mi[c]) - acc.comp[c];
+                const A t = acc.dl[c] + y;
+                acc.comp[c] = (t - acc.dl[c]) - y;
+                acc.dl[c] = t;
             } else {
-                mo[c] = static_cast<double>(mi[c]) + a.beta * static_cast<double>(dl[c]);
+                acc.dl[c] += static_cast<A>(w) * static_cast<A>(mj - acc.mi[c]);
             }
         }
-        if (NS == 3 && a.k_react > 0.0)
-            react3(mo, a);
+    }
+}
+
+// Candidates of one halo row segment: slots [gb, gb + len), staged at LDS
+// offset off when LDS is true.  Only the x-window [xlo, xhi] is visited.
+template <int D, int PREC, int NS, bool TRANSFER, bool LDS, int CAP>
+__device__ __forceinline__ void scan_row(const SimArgs& a, const typename Types<PREC>::T (&lpos)[D][CAP],
+                                         const typename Types<PREC>::T* lsr, uint32_t off, uint32_t len,
+                                         uint32_t gb, const typename Types<PREC>::T* xi,
+                                         typename Types<PREC>::T xlo, typename Types<PREC>::T xhi,
+                                         uint32_t i, Acc<PREC, NS, TRANSFER>& acc)
+{
+    using T = typename Types<PREC>::T;
+    const T* gx0 = static_cast<const T*>(a.x[0]) + gb;
+    uint32_t lo = 0, hi = len;
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        const T v = LDS ? lpos[0][off + mid] : gx0[mid];
+        if (v < xlo)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    for (uint32_t k = lo; k < len; ++k) {
+        T xj[3];
+        xj[0] = LDS ? lpos[0][off + k] : gx0[k];
+        if (xj[0] > xhi)
+            break;
 #pragma unroll
-        for (int c = 0; c < NS; ++c) {
-            const M st = static_cast<M>(mo[c]);
-            static_cast<M*>(a.m_dst[c])[i] = st;
-            outv[c] = static_cast<double>(st);
+        for (int d = 1; d < D; ++d)
+            xj[d] = LDS ? lpos[d][off + k] : static_cast<const T*>(a.x[d])[gb + k];
+        T sj = T(0);
+        if (TRANSFER)
+            sj = LDS ? lsr[off + k] : static_cast<const T*>(a.srow)[gb + k];
+        visit<D, PREC, NS, TRANSFER>(a, xi, xj, sj, i, gb + k, acc);
+    }
+}
+
+template <int D, int PREC, int NS, bool TRANSFER>
+__device__ __forceinline__ void tile_body(const SimArgs& a, uint32_t blk)
+{
+    using T = typename Types<PREC>::T;
+    using M = typename Types<PREC>::M;
+    constexpr int CAP = TileCap<D, T>::value;
+    constexpr int planes = D == 3 ? 3 : 1;
+    __shared__ T lpos[D][CAP];
+    __shared__ T lsr[TRANSFER ? CAP : 1];
+    __shared__ uint32_t seg_gb[kMaxSegs];
+    __shared__ uint32_t seg_off[kMaxSegs + 1];
+    __shared__ uint32_t own_gb[kMaxTileRows];
+    __shared__ uint32_t own_pre[kMaxTileRows + 1];
+
+    const int tid = threadIdx.x;
+    const int nc0 = a.nc[0], nc1 = a.nc[1], nc2 = a.nc[2];
+    const uint32_t per_plane = a.tiles_x * a.tiles_y;
+    const int tz = static_cast<int>(blk / per_plane);
+    const uint32_t rem = blk - static_cast<uint32_t>(tz) * per_plane;
+    const int tyi = static_cast<int>(rem / a.tiles_x);
+    const int txi = static_cast<int>(rem - static_cast<uint32_t>(tyi) * a.tiles_x);
+    const int x0 = txi * a.tile[0];
+    const int x1 = min(x0 + a.tile[0], nc0);
+    const int y0 = tyi * a.tile[1];
+    const int y1 = min(y0 + a.tile[1], nc1);
+    const int nrow = y1 - y0;
+    const int rows = nrow + 2;
+    const int nseg = rows * planes;
+    const int xa = x0 > 0 ? x0 - 1 : 0;
+    const int xb = x1 < nc0 ? x1 + 1 : nc0;
+
+    // halo row segments: cells xa..xb-1 of rows y0-1..y1 (and planes tz-1..tz+1)
+    uint32_t slen = 0;
+    if (tid < nseg) {
+        const int pz = D == 3 ? tz - 1 + tid / rows : 0;
+        const int py = y0 - 1 + tid % rows;
+        uint32_t gb = 0;
+        if (py >= 0 && py < nc1 && pz >= 0 && pz < nc2) {
+            const uint32_t rb = (static_cast<uint32_t>(pz) * nc1 + py) * nc0;
+            gb = a.starts[rb + xa];
+            slen = a.starts[rb + xb] - gb;
         }
+        seg_gb[tid] = gb;
     }
-    // per-block mass sums, fixed order
+    uint32_t total;
+    const uint32_t soff = block_excl_scan(slen, &total);
+    if (tid < nseg)
+        seg_off[tid] = soff;
+    if (tid == 0)
+        seg_off[nseg] = total;
+    // own rows: cells x0..x1-1 of rows y0..y1-1 of plane tz
+    uint32_t olen = 0;
+    if (tid < nrow) {
+        const uint32_t rb = (static_cast<uint32_t>(D == 3 ? tz : 0) * nc1 + (y0 + tid)) * nc0;
+        const uint32_t gb = a.starts[rb + x0];
+        olen = a.starts[rb + x1] - gb;
+        own_gb[tid] = gb;
+    }
+    uint32_t own_total;
+    const uint32_t ooff = block_excl_scan(olen, &own_total);
+    if (tid < nrow)
+        own_pre[tid] = ooff;
+    if (tid == 0)
+        own_pre[nrow] = own_total;
+    __syncthreads();
+
+    const bool use_lds = total <= static_cast<uint32_t>(CAP);
+    if (use_lds) {
+        for (uint32_t idx = tid; idx < total; idx += kBlock) {
+            int lo = 0, hi = nseg - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (seg_off[mid] <= idx)
+                    lo = mid;
+                else
+                    hi = mid - 1;
+            }
+            const uint32_t g = seg_gb[lo] + (idx - seg_off[lo]);
 #pragma unroll
-    for (int c = 0; c < NS; ++c) {
-        const double t = block_sum<double>(outv[c]);
-        if (threadIdx.x == 0)
-            a.partials[static_cast<size_t>(blk) * NS + c] = t;
-    }
-    __shared__ int last;
-    if (threadIdx.x == 0) {
-        __threadfence();
-        const unsigned prev = atomicAdd(&a.st->blocks_done, 1u);
-        last = (prev == a.part_blocks - 1u);
+            for (int d = 0; d < D; ++d)
+                lpos[d][idx] = static_cast<const T*>(a.x[d])[g];
+            if (TRANSFER)
+                lsr[idx] = static_cast<const T*>(a.srow)[g];
+        }
     }
     __syncthreads();
-    if (!last)
-        return;
-    __threadfence();
-    const volatile double* part = a.partials;
+
+    uint32_t pairs = 0;
+    double msum[NS];
 #pragma unroll
-    for (int c = 0; c < NS; ++c) {
-        double s = 0.0;
-        for (uint32_t b = threadIdx.x; b < a.part_blocks; b += kBlock)
-            s += part[static_cast<size_t>(b) * NS + c];
-        const double t = block_sum<double>(s);
-        if (threadIdx.x == 0) {
-            a.st->totals[c] = t;
-            if (!isfinite(t))
-                a.st->nonfinite = 1;
+    for (int c = 0; c < NS; ++c)
+        msum[c] = 0.0;
+    for (uint32_t t = tid; t < own_total; t += kBlock) {
+        int r = 0, hi = nrow - 1;
+        while (r < hi) {
+            const int mid = (r + hi + 1) >> 1;
+            if (own_pre[mid] <= t)
+                r = mid;
+            else
+                hi = mid - 1;
+        }
+        const uint32_t i = own_gb[r] + (t - own_pre[r]);
+        T xi[3];
+#pragma unroll
+        for (int d = 0; d < D; ++d)
+            xi[d] = static_cast<const T*>(a.x[d])[i];
+        T xlo, xhi;
+        Window<T>::make(xi[0], a.win, &xlo, &xhi);
+        Acc<PREC, NS, TRANSFER> acc;
+        if constexpr (TRANSFER) {
+            acc.si = static_cast<const T*>(a.srow)[i];
+#pragma unroll
+            for (int c = 0; c < NS; ++c) {
+                acc.mi[c] = static_cast<const M*>(a.m_mid[c])[i];
+                acc.dl[c] = 0;
+                acc.comp[c] = 0;
+            }
+        }
+#pragma unroll
+        for (int pzr = 0; pzr < planes; ++pzr) {
+#pragma unroll
+            for (int dy = 0; dy < 3; ++dy) {
+                const int s = pzr * rows + r + dy;
+                const uint32_t off = seg_off[s];
+                const uint32_t len = seg_off[s + 1] - off;
+                if (len == 0)
+                    continue;
+                if (use_lds)
+                    scan_row<D, PREC, NS, TRANSFER, true, CAP>(a, lpos, lsr, off, len, seg_gb[s], xi, xlo,
+                                                               xhi, i, acc);
+                else
+                    scan_row<D, PREC, NS, TRANSFER, false, CAP>(a, lpos, lsr, off, len, seg_gb[s], xi,
+                                                                xlo, xhi, i, acc);
+            }
+        }
+        if constexpr (!TRANSFER) {
+            static_cast<T*>(a.srow)[i] = acc.s;
+            pairs += acc.cnt - 1u;
+        } else {
+            double mo[3];
+#pragma unroll
+            for (int c = 0; c < NS; ++c) {
+                if (PREC == 2) {
+                    const float nv = acc.mi[c] + a.betaf * acc.dl[c];
+                    mo[c] = static_cast<double>(nv);
+                } else {
+                    mo[c] = static_cast<double>(acc.mi[c]) + a.beta * static_cast<double>(acc.dl[c]);
+                }
+            }
+            if (NS == 3 && a.k_react > 0.0)
+                react3(mo, a);
+#pragma unroll
+            for (int c = 0; c < NS; ++c) {
+                const M st = static_cast<M>(mo[c]);
+                static_cast<M*>(a.m_dst[c])[i] = st;
+                msum[c] += static_cast<double>(st);
+            }
         }
     }
-    if (threadIdx.x == 0) {
-        DevStats* st = a.st;
-        if (a.recompute_s) {
-            st->pairs_last = st->pairs_acc;
-            st->pairs_acc = 0ull;
+    if constexpr (!TRANSFER) {
+        const uint32_t p = block_sum<kBlock, uint32_t>(pairs);
+        if (tid == 0)
+            a.pair_part[blk] = p;
+    } else {
+#pragma unroll
+        for (int c = 0; c < NS; ++c) {
+            const double t = block_sum<kBlock, double>(msum[c]);
+            if (tid == 0)
+                a.partials[static_cast<size_t>(blk) * NS + c] = t;
         }
+    }
+}
+
+// Totals and pair counters of one step (mode 0) or totals only (mode 1),
+// summed over the per-workgroup partials in a fixed order.
+__device__ __forceinline__ void finalize_body(const SimArgs& a, uint32_t nparts, int mode)
+{
+    const int ns = a.ns;
+    DevStats* st = a.st;
+    unsigned long long pairs = 0;
+    if (mode == 0 && a.recompute_s) {
+        unsigned long long p = 0;
+        for (uint32_t b = threadIdx.x; b < nparts; b += kFinalBlock)
+            p += a.pair_part[b];
+        pairs = block_sum<kFinalBlock, unsigned long long>(p);
+    }
+    for (int c = 0; c < ns; ++c) {
+        double s = 0.0;
+        for (uint32_t b = threadIdx.x; b < nparts; b += kFinalBlock)
+            s += a.partials[static_cast<size_t>(b) * ns + c];
+        const double t = block_sum<kFinalBlock, double>(s);
+        if (threadIdx.x == 0) {
+            st->totals[c] = t;
+            if (!isfinite(t))
+                st->nonfinite = 1;
+        }
+    }
+    if (threadIdx.x == 0 && mode == 0) {
+        if (a.recompute_s)
+            st->pairs_last = pairs;
         st->pairs_total += st->pairs_last;
         st->steps += 1;
-        st->blocks_done = 0u;
-        __threadfence();
     }
 }
 
@@ -533,85 +705,58 @@ __device__ __forceinline__ int find_sim(const Batch& b, uint32_t blk, uint32_t* 
     return lo;
 }
 
+#define MTPT_BATCH_PROLOGUE                                                                     \
+    uint32_t l;                                                                                 \
+    const SimArgs& a = b.args[find_sim(b, blockIdx.x, &l)]
+
 template <int D, typename T>
 __global__ __launch_bounds__(kBlock) void bin_k(SimArgs a) { bin_body<D, T>(a, blockIdx.x); }
 template <int D, typename T>
-__global__ __launch_bounds__(kBlock) void bin_kb(Batch b)
-{
-    uint32_t l;
-    const SimArgs& a = b.args[find_sim(b, blockIdx.x, &l)];
-    bin_body<D, T>(a, l);
-}
+__global__ __launch_bounds__(kBlock) void bin_kb(Batch b) { MTPT_BATCH_PROLOGUE; bin_body<D, T>(a, l); }
 
 __global__ __launch_bounds__(kBlock) void scan_reduce_k(SimArgs a) { scan_reduce_body(a.counts, a.bsum, blockIdx.x); }
-__global__ __launch_bounds__(kBlock) void scan_reduce_kb(Batch b)
-{
-    uint32_t l;
-    const SimArgs& a = b.args[find_sim(b, blockIdx.x, &l)];
-    scan_reduce_body(a.counts, a.bsum, l);
-}
+__global__ __launch_bounds__(kBlock) void scan_reduce_kb(Batch b) { MTPT_BATCH_PROLOGUE; scan_reduce_body(a.counts, a.bsum, l); }
 __global__ __launch_bounds__(kBlock) void scan_top_k(SimArgs a) { scan_top_body(a.bsum, a.scan_blocks); }
-__global__ __launch_bounds__(kBlock) void scan_top_kb(Batch b)
-{
-    uint32_t l;
-    const SimArgs& a = b.args[find_sim(b, blockIdx.x, &l)];
-    scan_top_body(a.bsum, a.scan_blocks);
-}
+__global__ __launch_bounds__(kBlock) void scan_top_kb(Batch b) { MTPT_BATCH_PROLOGUE; (void)l; scan_top_body(a.bsum, a.scan_blocks); }
 __global__ __launch_bounds__(kBlock) void scan_down_k(SimArgs a) { scan_down_body(a.counts, a.starts, a.bsum, blockIdx.x, true); }
-__global__ __launch_bounds__(kBlock) void scan_down_kb(Batch b)
-{
-    uint32_t l;
-    const SimArgs& a = b.args[find_sim(b, blockIdx.x, &l)];
-    scan_down_body(a.counts, a.starts, a.bsum, l, true);
-}
-
+__global__ __launch_bounds__(kBlock) void scan_down_kb(Batch b) { MTPT_BATCH_PROLOGUE; scan_down_body(a.counts, a.starts, a.bsum, l, true); }
 __global__ __launch_bounds__(kBlock) void scatter_k(SimArgs a) { scatter_body(a, blockIdx.x); }
-__global__ __launch_bounds__(kBlock) void scatter_kb(Batch b)
+__global__ __launch_bounds__(kBlock) void scatter_kb(Batch b) { MTPT_BATCH_PROLOGUE; scatter_body(a, l); }
+
+template <int D, int PREC>
+__global__ __launch_bounds__(kBlock) void place_k(SimArgs a)
 {
-    uint32_t l;
-    const SimArgs& a = b.args[find_sim(b, blockIdx.x, &l)];
-    scatter_body(a, l);
+    place_body<D, typename Types<PREC>::T, typename Types<PREC>::M>(a, blockIdx.x);
 }
-__global__ __launch_bounds__(kBlock) void cellsort_k(SimArgs a) { cellsort_body(a, blockIdx.x); }
-__global__ __launch_bounds__(kBlock) void cellsort_kb(Batch b)
+template <int D, int PREC>
+__global__ __launch_bounds__(kBlock) void place_kb(Batch b)
 {
-    uint32_t l;
-    const SimArgs& a = b.args[find_sim(b, blockIdx.x, &l)];
-    cellsort_body(a, l);
+    MTPT_BATCH_PROLOGUE;
+    place_body<D, typename Types<PREC>::T, typename Types<PREC>::M>(a, l);
 }
 
 template <int D, int PREC>
-__global__ __launch_bounds__(kBlock) void gather_k(SimArgs a)
-{
-    gather_body<D, typename Types<PREC>::T, typename Types<PREC>::M>(a, blockIdx.x);
-}
+__global__ __launch_bounds__(kBlock) void rowsum_k(SimArgs a) { tile_body<D, PREC, 1, false>(a, blockIdx.x); }
 template <int D, int PREC>
-__global__ __launch_bounds__(kBlock) void gather_kb(Batch b)
-{
-    uint32_t l;
-    const SimArgs& a = b.args[find_sim(b, blockIdx.x, &l)];
-    gather_body<D, typename Types<PREC>::T, typename Types<PREC>::M>(a, l);
-}
-
-template <int D, int PREC>
-__global__ __launch_bounds__(kBlock) void rowsum_k(SimArgs a) { rowsum_body<D, PREC>(a, blockIdx.x); }
-template <int D, int PREC>
-__global__ __launch_bounds__(kBlock) void rowsum_kb(Batch b)
-{
-    uint32_t l;
-    const SimArgs& a = b.args[find_sim(b, blockIdx.x, &l)];
-    rowsum_body<D, PREC>(a, l);
-}
+__global__ __launch_bounds__(kBlock) void rowsum_kb(Batch b) { MTPT_BATCH_PROLOGUE; tile_body<D, PREC, 1, false>(a, l); }
 
 template <int D, int PREC, int NS>
-__global__ __launch_bounds__(kBlock) void transfer_k(SimArgs a) { transfer_body<D, PREC, NS>(a, blockIdx.x); }
+__global__ __launch_bounds__(kBlock) void transfer_k(SimArgs a) { tile_body<D, PREC, NS, true>(a, blockIdx.x); }
 template <int D, int PREC, int NS>
-__global__ __launch_bounds__(kBlock) void transfer_kb(Batch b)
+__global__ __launch_bounds__(kBlock) void transfer_kb(Batch b) { MTPT_BATCH_PROLOGUE; tile_body<D, PREC, NS, true>(a, l); }
+
+__global__ __launch_bounds__(kFinalBlock) void finalize_k(SimArgs a, uint32_t nparts, int mode)
 {
-    uint32_t l;
-    const SimArgs& a = b.args[find_sim(b, blockIdx.x, &l)];
-    transfer_body<D, PREC, NS>(a, l);
+    finalize_body(a, nparts, mode);
 }
+__global__ __launch_bounds__(kFinalBlock) void finalize_kb(Batch b)
+{
+    MTPT_BATCH_PROLOGUE;
+    (void)l;
+    finalize_body(a, a.ntiles, 0);
+}
+
+#undef MTPT_BATCH_PROLOGUE
 
 // ----------------------------------------------------------------- exports
 template <typename M>
@@ -643,8 +788,7 @@ __global__ __launch_bounds__(kBlock) void unpermute_pos_k(int64_t n, const T* x0
         out[p * D + 2] = static_cast<double>(x2[k]);
 }
 
-// totals of the current masses: per-block sums, then the last block sums
-// them in block order (same scheme as the transfer pass)
+// per-block sums of the current masses (then finalize in totals-only mode)
 template <typename M>
 __global__ __launch_bounds__(kBlock) void totals_k(SimArgs a, const M* m0, const M* m1, const M* m2)
 {
@@ -652,34 +796,36 @@ __global__ __launch_bounds__(kBlock) void totals_k(SimArgs a, const M* m0, const
     const M* ms[3] = {m0, m1, m2};
     for (int c = 0; c < a.ns; ++c) {
         const double v = i < a.n ? static_cast<double>(ms[c][i]) : 0.0;
-        const double t = block_sum<double>(v);
+        const double t = block_sum<kBlock, double>(v);
         if (threadIdx.x == 0)
             a.partials[static_cast<size_t>(blockIdx.x) * a.ns + c] = t;
     }
-    __shared__ int last;
-    if (threadIdx.x == 0) {
-        __threadfence();
-        const unsigned prev = atomicAdd(&a.st->blocks_done, 1u);
-        last = (prev == a.part_blocks - 1u);
-    }
-    __syncthreads();
-    if (!last)
-        return;
-    __threadfence();
-    const volatile double* part = a.partials;
-    for (int c = 0; c < a.ns; ++c) {
-        double s = 0.0;
-        for (uint32_t b = threadIdx.x; b < a.part_blocks; b += kBlock)
-            s += part[static_cast<size_t>(b) * a.ns + c];
-        const double t = block_sum<double>(s);
-        if (threadIdx.x == 0) {
-            a.st->totals[c] = t;
-            if (!isfinite(t))
-                a.st->nonfinite = 1;
+}
+
+// The neighbour export walks the full 3^d cells around each particle
+// (independent of the tiles and windows of the hot passes).
+template <int D, typename T, typename F>
+__device__ __forceinline__ void for_candidates(const SimArgs& a, const T* xi, F&& f)
+{
+    int cc[3];
+#pragma unroll
+    for (int k = 0; k < D; ++k)
+        cc[k] = cell_coord(static_cast<double>(xi[k]), a.glo[k], a.inv_side[k], a.nc[k]);
+    const int x0 = cc[0] > 0 ? cc[0] - 1 : 0;
+    const int x1 = cc[0] < a.nc[0] - 1 ? cc[0] + 1 : a.nc[0] - 1;
+    const int zlo = (D == 3) ? (cc[2] > 0 ? cc[2] - 1 : 0) : 0;
+    const int zhi = (D == 3) ? (cc[2] < a.nc[2] - 1 ? cc[2] + 1 : a.nc[2] - 1) : 0;
+    const int ylo = cc[1] > 0 ? cc[1] - 1 : 0;
+    const int yhi = cc[1] < a.nc[1] - 1 ? cc[1] + 1 : a.nc[1] - 1;
+    for (int z = zlo; z <= zhi; ++z) {
+        for (int y = ylo; y <= yhi; ++y) {
+            const uint32_t row = (static_cast<uint32_t>(z) * a.nc[1] + y) * a.nc[0];
+            const uint32_t j0 = a.starts[row + x0];
+            const uint32_t j1 = a.starts[row + x1 + 1];
+            for (uint32_t j = j0; j < j1; ++j)
+                f(j);
         }
     }
-    if (threadIdx.x == 0)
-        a.st->blocks_done = 0u;
 }
 
 template <int D, int PREC>
@@ -729,7 +875,6 @@ __global__ __launch_bounds__(kBlock) void nb_fill_k(SimArgs a, const uint32_t* p
         if (Pair<D, T>::inside(a, xi, xj, &r2))
             col[base + cnt++] = static_cast<int64_t>(pid[j]);
     });
-    // ascending pid inside the row
     for (int64_t k = 1; k < cnt; ++k) {
         const int64_t v = col[base + k];
         int64_t j = k;
@@ -741,9 +886,8 @@ __global__ __launch_bounds__(kBlock) void nb_fill_k(SimArgs a, const uint32_t* p
     }
 }
 
-// exclusive scan of n u32 counts into int64 offsets (n+1 values): the
-// counts are copied into a tile-padded buffer, scanned like the histogram,
-// and widened
+// exclusive scan of n u32 counts into int64 offsets (n+1 values): copy into a
+// tile-padded buffer, scan like the histogram, widen
 __global__ __launch_bounds__(kBlock) void widen_k(const uint32_t* in, int64_t* out, int64_t len)
 {
     const int64_t k = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
@@ -767,33 +911,44 @@ __global__ __launch_bounds__(kBlock) void scan_down_raw_k(uint32_t* in, uint32_t
 const char* phase_name(int ph)
 {
     static const char* names[PH_COUNT] = {"bin", "scan_reduce", "scan_top", "scan_down", "scatter",
-                                          "cellsort", "gather", "rowsum", "transfer"};
+                                          "place", "rowsum", "transfer", "finalize"};
     return (ph >= 0 && ph < PH_COUNT) ? names[ph] : "?";
+}
+
+int tile_capacity(int dim, int prec)
+{
+    if (dim == 2)
+        return prec == 0 ? TileCap<2, double>::value : TileCap<2, float>::value;
+    return prec == 0 ? TileCap<3, double>::value : TileCap<3, float>::value;
 }
 
 static uint32_t ceil_div(int64_t a, int64_t b) { return static_cast<uint32_t>((a + b - 1) / b); }
 
 uint32_t phase_blocks(int ph, const SimArgs& a)
 {
+    if (a.n <= 0)
+        return 0;
     switch (ph) {
     case PH_SCAN_REDUCE:
     case PH_SCAN_DOWN: return a.scan_blocks;
-    case PH_SCAN_TOP: return 1;
-    case PH_CELLSORT: return ceil_div(a.ncells, kBlock);
-    default: return a.n > 0 ? ceil_div(a.n, kBlock) : 0;
+    case PH_SCAN_TOP:
+    case PH_FINALIZE: return 1;
+    case PH_ROWSUM:
+    case PH_TRANSFER: return a.ntiles;
+    default: return ceil_div(a.n, kBlock);
     }
 }
 
-#define MTPT_DISPATCH_D_PREC(KERNEL, GRID, ARG)                                                  \
+#define MTPT_DISPATCH_D_PREC(KERNEL, GRID, NT, ARG)                                              \
     do {                                                                                         \
         if (dim == 2) {                                                                          \
-            if (prec == 0) KERNEL<2, 0><<<GRID, kBlock, 0, s>>>(ARG);                            \
-            else if (prec == 1) KERNEL<2, 1><<<GRID, kBlock, 0, s>>>(ARG);                       \
-            else KERNEL<2, 2><<<GRID, kBlock, 0, s>>>(ARG);                                      \
+            if (prec == 0) KERNEL<2, 0><<<GRID, NT, 0, s>>>(ARG);                                \
+            else if (prec == 1) KERNEL<2, 1><<<GRID, NT, 0, s>>>(ARG);                           \
+            else KERNEL<2, 2><<<GRID, NT, 0, s>>>(ARG);                                          \
         } else {                                                                                 \
-            if (prec == 0) KERNEL<3, 0><<<GRID, kBlock, 0, s>>>(ARG);                            \
-            else if (prec == 1) KERNEL<3, 1><<<GRID, kBlock, 0, s>>>(ARG);                       \
-            else KERNEL<3, 2><<<GRID, kBlock, 0, s>>>(ARG);                                      \
+            if (prec == 0) KERNEL<3, 0><<<GRID, NT, 0, s>>>(ARG);                                \
+            else if (prec == 1) KERNEL<3, 1><<<GRID, NT, 0, s>>>(ARG);                           \
+            else KERNEL<3, 2><<<GRID, NT, 0, s>>>(ARG);                                          \
         }                                                                                        \
     } while (0)
 
@@ -842,10 +997,10 @@ hipError_t launch_phase(int ph, int dim, int prec, const SimArgs& a, hipStream_t
     case PH_SCAN_TOP: scan_top_k<<<1, kBlock, 0, s>>>(a); break;
     case PH_SCAN_DOWN: scan_down_k<<<grid, kBlock, 0, s>>>(a); break;
     case PH_SCATTER: scatter_k<<<grid, kBlock, 0, s>>>(a); break;
-    case PH_CELLSORT: cellsort_k<<<grid, kBlock, 0, s>>>(a); break;
-    case PH_GATHER: MTPT_DISPATCH_D_PREC(gather_k, grid, a); break;
-    case PH_ROWSUM: MTPT_DISPATCH_D_PREC(rowsum_k, grid, a); break;
+    case PH_PLACE: MTPT_DISPATCH_D_PREC(place_k, grid, kBlock, a); break;
+    case PH_ROWSUM: MTPT_DISPATCH_D_PREC(rowsum_k, grid, kBlock, a); break;
     case PH_TRANSFER: MTPT_DISPATCH_D_PREC_NS(transfer_k, grid, a); break;
+    case PH_FINALIZE: finalize_k<<<1, kFinalBlock, 0, s>>>(a, a.ntiles, 0); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -870,10 +1025,10 @@ hipError_t launch_phase_batched(int ph, int dim, int prec, int ns, const Batch& 
     case PH_SCAN_TOP: scan_top_kb<<<grid, kBlock, 0, s>>>(b); break;
     case PH_SCAN_DOWN: scan_down_kb<<<grid, kBlock, 0, s>>>(b); break;
     case PH_SCATTER: scatter_kb<<<grid, kBlock, 0, s>>>(b); break;
-    case PH_CELLSORT: cellsort_kb<<<grid, kBlock, 0, s>>>(b); break;
-    case PH_GATHER: MTPT_DISPATCH_D_PREC(gather_kb, grid, b); break;
-    case PH_ROWSUM: MTPT_DISPATCH_D_PREC(rowsum_kb, grid, b); break;
+    case PH_PLACE: MTPT_DISPATCH_D_PREC(place_kb, grid, kBlock, b); break;
+    case PH_ROWSUM: MTPT_DISPATCH_D_PREC(rowsum_kb, grid, kBlock, b); break;
     case PH_TRANSFER: MTPT_DISPATCH_D_PREC_NS(transfer_kb, grid, b); break;
+    case PH_FINALIZE: finalize_kb<<<grid, kFinalBlock, 0, s>>>(b); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -929,6 +1084,7 @@ hipError_t launch_totals(int prec, const SimArgs& a, const void* const* m_cur, h
         totals_k<double><<<grid, kBlock, 0, s>>>(a, static_cast<const double*>(m_cur[0]),
                                                  static_cast<const double*>(m_cur[1]),
                                                  static_cast<const double*>(m_cur[2]));
+    finalize_k<<<1, kFinalBlock, 0, s>>>(a, grid, 1);
     return hipGetLastError();
 }
 

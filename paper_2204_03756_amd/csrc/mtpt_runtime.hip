@@ -82,9 +82,12 @@ struct Plan {
     double inv_side[3] = {0, 0, 0};
     uint32_t ncells = 1;
     uint32_t scan_blocks = 1, part_blocks = 0;
+    int tile[2] = {1, 1};
+    uint32_t tiles_x = 1, tiles_y = 1, ntiles = 0;
     size_t tsz = 8, msz = 8;
     size_t off_x[3]{}, off_xt[3]{}, off_m[2][3]{}, off_p[2]{}, off_s = 0, off_cell = 0, off_rank = 0,
-           off_perm = 0, off_counts = 0, off_starts = 0, off_bsum = 0, off_part = 0, off_stats = 0;
+           off_perm = 0, off_counts = 0, off_starts = 0, off_bsum = 0, off_part = 0, off_pair = 0,
+           off_stats = 0;
     size_t bytes = 0;
 };
 
@@ -161,6 +164,29 @@ Plan make_plan(const mtpt_params& p)
     }
     q.scan_blocks = static_cast<uint32_t>((static_cast<uint64_t>(q.ncells) + 1 + kScanTile - 1) / kScanTile);
     q.part_blocks = static_cast<uint32_t>((q.n + kBlock - 1) / kBlock);
+    // tiles of the mass-transfer passes: about one particle per thread, and
+    // the tile plus its one-cell halo expected to fill at most 1/1.6 of the
+    // LDS staging capacity (a fuller tile falls back to global reads)
+    {
+        const double rho_c = static_cast<double>(q.n) / static_cast<double>(q.ncells);
+        const int planes = q.dim == 3 ? 3 : 1;
+        const double cap = static_cast<double>(tile_capacity(q.dim, q.prec)) / 1.6;
+        const double cells_own = std::max(1.0, 224.0 / std::max(rho_c, 1e-9));
+        int t = static_cast<int>(std::lround(std::sqrt(cells_own)));
+        int tx = std::max(1, std::min(t, std::min(q.nc[0], 4096)));
+        int ty = std::max(1, std::min(t, std::min(q.nc[1], kMaxTileRows)));
+        while ((tx + 2.0) * (ty + 2.0) * planes * rho_c > cap && (tx > 1 || ty > 1)) {
+            if (tx >= ty)
+                --tx;
+            else
+                --ty;
+        }
+        q.tile[0] = tx;
+        q.tile[1] = ty;
+        q.tiles_x = static_cast<uint32_t>((q.nc[0] + tx - 1) / tx);
+        q.tiles_y = static_cast<uint32_t>((q.nc[1] + ty - 1) / ty);
+        q.ntiles = q.tiles_x * q.tiles_y * static_cast<uint32_t>(q.dim == 3 ? q.nc[2] : 1);
+    }
     const size_t n = static_cast<size_t>(q.n);
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -185,7 +211,8 @@ Plan make_plan(const mtpt_params& p)
     q.off_counts = take(padded * 4);
     q.off_starts = take(padded * 4);
     q.off_bsum = take(static_cast<size_t>(q.scan_blocks) * 4);
-    q.off_part = take(static_cast<size_t>(std::max<uint32_t>(q.part_blocks, 1)) * 3 * 8);
+    q.off_part = take(static_cast<size_t>(std::max<uint32_t>(std::max(q.part_blocks, q.ntiles), 1)) * 3 * 8);
+    q.off_pair = take(static_cast<size_t>(std::max<uint32_t>(q.ntiles, 1)) * 4);
     q.off_stats = take(sizeof(DevStats));
     q.bytes = off;
     return q;
@@ -213,6 +240,7 @@ struct mtpt_sim {
     uint32_t *cell = nullptr, *rank = nullptr, *perm = nullptr, *counts = nullptr, *starts = nullptr,
              *bsum = nullptr;
     double* partials = nullptr;
+    uint32_t* pair_part = nullptr;
     DevStats* st = nullptr;
     int64_t steps_done = 0;   // steps enqueued since create
     bool moving = false;
@@ -250,6 +278,7 @@ void carve(mtpt_sim* s)
     s->starts = reinterpret_cast<uint32_t*>(b + q.off_starts);
     s->bsum = reinterpret_cast<uint32_t*>(b + q.off_bsum);
     s->partials = reinterpret_cast<double*>(b + q.off_part);
+    s->pair_part = reinterpret_cast<uint32_t*>(b + q.off_pair);
     s->st = reinterpret_cast<DevStats*>(b + q.off_stats);
 }
 
@@ -272,9 +301,16 @@ SimArgs base_args(const mtpt_sim* s)
         a.hif[k] = static_cast<float>(p.hi[k]);
     }
     a.ncells = q.ncells;
+    a.tile[0] = q.tile[0];
+    a.tile[1] = q.tile[1];
+    a.tiles_x = q.tiles_x;
+    a.tiles_y = q.tiles_y;
+    a.ntiles = q.ntiles;
     a.sdev = std::sqrt(2.0 * p.d_rw * p.dt);
     a.seed = p.seed;
+    a.psi = q.psi;
     a.psi2 = q.psi * q.psi;
+    a.win = q.psi * (1.0 + 1e-6);
     a.psi2_in = static_cast<float>(a.psi2 * (1.0 - 1e-5));
     a.psi2_out = static_cast<float>(a.psi2 * (1.0 + 1e-5));
     a.kc = p.beta / (4.0 * p.d_mt * p.dt);
@@ -300,6 +336,7 @@ SimArgs base_args(const mtpt_sim* s)
     a.starts = s->starts;
     a.bsum = s->bsum;
     a.partials = s->partials;
+    a.pair_part = s->pair_part;
     a.st = s->st;
     a.scan_blocks = q.scan_blocks;
     a.part_blocks = q.part_blocks;
@@ -362,7 +399,7 @@ int launch(mtpt_sim* s, int ph, const SimArgs& a)
 int enqueue_binning(mtpt_sim* s, const SimArgs& a)
 {
     static const int phases[] = {PH_BIN, PH_SCAN_REDUCE, PH_SCAN_TOP, PH_SCAN_DOWN,
-                                 PH_SCATTER, PH_CELLSORT, PH_GATHER};
+                                 PH_SCATTER, PH_PLACE};
     for (int ph : phases) {
         const int rc = launch(s, ph, a);
         if (rc)
@@ -385,7 +422,10 @@ int enqueue_step(mtpt_sim* s)
         if (rc)
             return rc;
     }
-    const int rc = launch(s, PH_TRANSFER, a);
+    int rc = launch(s, PH_TRANSFER, a);
+    if (rc)
+        return rc;
+    rc = launch(s, PH_FINALIZE, a);
     if (rc)
         return rc;
     s->steps_done += 1;
@@ -1006,10 +1046,11 @@ int mtpt_pool_tick(mtpt_pool* p, int32_t* n_completed)
             const uint32_t* hpre = reinterpret_cast<const uint32_t*>(h + align_up(goff[gi] + ns * sizeof(SimArgs), 256));
             std::vector<int> phases;
             if (k.moving)
-                phases = {PH_BIN, PH_SCAN_REDUCE, PH_SCAN_TOP, PH_SCAN_DOWN, PH_SCATTER, PH_CELLSORT, PH_GATHER};
+                phases = {PH_BIN, PH_SCAN_REDUCE, PH_SCAN_TOP, PH_SCAN_DOWN, PH_SCATTER, PH_PLACE};
             if (k.rowsum)
                 phases.push_back(PH_ROWSUM);
             phases.push_back(PH_TRANSFER);
+            phases.push_back(PH_FINALIZE);
             for (int ph : phases) {
                 Batch b;
                 b.args = dargs;
