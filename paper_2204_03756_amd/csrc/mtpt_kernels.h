@@ -27,8 +27,17 @@ constexpr int kBlock = 256;          // threads per workgroup, 4 wave64s
 constexpr int kScanItems = 16;       // counts per thread in the scan
 constexpr int kScanTile = kBlock * kScanItems;
 constexpr int kFinalBlock = 1024;    // threads of the finalize kernel
-constexpr int kMaxTileRows = 64;     // tile extent in y, cells
-constexpr int kMaxSegs = 3 * (kMaxTileRows + 2);
+constexpr int kLdsBudget = 24576;    // bytes of staged particle data per workgroup
+
+// Largest tile (cells in x and in y) of the mass-transfer passes, the halo
+// cell rows it spans and the cell boundaries kept per halo row.
+template <int D> struct TileLimits {
+    static constexpr int max_x = D == 2 ? 32 : 16;
+    static constexpr int max_y = D == 2 ? 32 : 16;
+    static constexpr int segs = (D == 3 ? 3 : 1) * (max_y + 2);
+    static constexpr int cols = max_x + 3;
+};
+inline int tile_max(int dim) { return dim == 2 ? TileLimits<2>::max_x : TileLimits<3>::max_x; }
 
 struct DevStats {
     unsigned long long pairs_last;   // pairs of the last step
@@ -68,7 +77,9 @@ struct SimArgs {
     float psi2_out;          // FP32 r^2 above this: outside for sure
     double kc;
     float kcf;
+    float kcf2;              // -kc log2(e): K = 2^(kcf2 r^2) in FP32
     float betaf;
+    float pad2;
     double beta;
     double k_react, to_c, to_m, dt;
     // buffers
@@ -93,6 +104,8 @@ struct SimArgs {
     uint32_t part_blocks;    // ceil(n / kBlock)
     int32_t recompute_s;     // the row-sum pass ran this step
     int32_t walk;            // apply the jump in the bin pass (0 at create)
+    int32_t fuse_bin;        // the transfer pass also bins for the next step
+    int32_t pad1;
 };
 
 // Batched launches: a device array of SimArgs and a device prefix of blocks
@@ -119,8 +132,9 @@ enum Phase {
 
 const char* phase_name(int ph);
 
-// particles of positions staged per workgroup in the tiled passes
-int tile_capacity(int dim, int prec);
+// particles staged per workgroup by the transfer pass (the tighter of the
+// two tiled passes)
+int tile_capacity(int dim, int prec, int ns);
 
 // blocks a phase needs for one sim
 uint32_t phase_blocks(int ph, const SimArgs& a);

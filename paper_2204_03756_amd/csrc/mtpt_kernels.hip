@@ -33,9 +33,14 @@ template <> struct Types<0> { using T = double; using M = double; using A = doub
 template <> struct Types<1> { using T = float;  using M = double; using A = double; };
 template <> struct Types<2> { using T = float;  using M = float;  using A = float;  };
 
-// positions staged per workgroup (tile cells plus halo)
-template <int D, typename T> struct TileCap {
-    static constexpr int value = D == 2 ? 1024 : (sizeof(T) == 8 ? 1536 : 2560);
+// particles staged per workgroup (tile cells plus halo): positions, and for
+// the transfer pass also row sums and masses, within kLdsBudget bytes
+template <int D, int PREC, int NS, bool TRANSFER> struct TileCap {
+    using T = typename Types<PREC>::T;
+    using M = typename Types<PREC>::M;
+    static constexpr int bytes =
+        D * static_cast<int>(sizeof(T)) + (TRANSFER ? static_cast<int>(sizeof(T) + NS * sizeof(M)) : 0);
+    static constexpr int value = kLdsBudget / bytes;
 };
 
 __device__ __forceinline__ int cell_coord(double x, double glo, double inv, int nc)
@@ -93,19 +98,23 @@ template <int D> struct Pair<D, float> {
             r2 = r2 + d2 * d2;
         }
         *r2o = r2;
-        if (r2 < a.psi2_in)
-            return true;
-        if (r2 > a.psi2_out)
-            return false;
-        double pi[3], pj[3];
+        bool in = r2 < a.psi2_in;
+        const bool band = (r2 >= a.psi2_in) & (r2 <= a.psi2_out);
+        if (__builtin_expect(band, 0)) {
+            double pi[3], pj[3];
 #pragma unroll
-        for (int k = 0; k < D; ++k) {
-            pi[k] = static_cast<double>(xi[k]);
-            pj[k] = static_cast<double>(xj[k]);
+            for (int k = 0; k < D; ++k) {
+                pi[k] = static_cast<double>(xi[k]);
+                pj[k] = static_cast<double>(xj[k]);
+            }
+            in = r2_canonical<D>(pi, pj) <= a.psi2;
         }
-        return r2_canonical<D>(pi, pj) <= a.psi2;
+        return in;
     }
-    __device__ __forceinline__ static float kernel(const SimArgs& a, float r2) { return __expf(-a.kcf * r2); }
+    __device__ __forceinline__ static float kernel(const SimArgs& a, float r2)
+    {
+        return __builtin_amdgcn_exp2f(a.kcf2 * r2);
+    }
     __device__ __forceinline__ static float weight(float k, float si, float sj)
     {
         return (k + k) * __builtin_amdgcn_rcpf(si + sj);
@@ -412,92 +421,100 @@ template <int PREC, int NS> struct Acc<PREC, NS, true> {
     A comp[NS];
 };
 
-// One candidate j (global slot) with position xj and row sum sj (transfer).
-template <int D, int PREC, int NS, bool TRANSFER>
-__device__ __forceinline__ void visit(const SimArgs& a, const typename Types<PREC>::T* xi,
-                                      const typename Types<PREC>::T* xj, typename Types<PREC>::T sj,
-                                      uint32_t i, uint32_t j, Acc<PREC, NS, TRANSFER>& acc)
+// Candidates of one halo row: positions p[k] (k in [b, e), x-sorted), and for
+// the transfer pass row sums sr[k] and masses ms[c][k]; slot j = k + jofs.
+// Only the x-window [xlo, xhi] is visited.
+template <int D, int PREC, int NS, bool TRANSFER, typename PX, typename PS, typename PM>
+__device__ __forceinline__ void scan_row(const SimArgs& a, PX p, PS sr, PM ms, uint32_t b, uint32_t e,
+                                         uint32_t jofs, const typename Types<PREC>::T* xi,
+                                         typename Types<PREC>::T xlo, typename Types<PREC>::T xhi,
+                                         uint32_t i, Acc<PREC, NS, TRANSFER>& acc)
 {
     using T = typename Types<PREC>::T;
     using M = typename Types<PREC>::M;
     using A = typename Types<PREC>::A;
-    if (TRANSFER) {
-        if (j == i)
-            return;
-    }
-    T r2;
-    if (!Pair<D, T>::inside(a, xi, xj, &r2))
-        return;
-    const T kv = Pair<D, T>::kernel(a, r2);
-    if constexpr (!TRANSFER) {
-        acc.s += kv;
-        acc.cnt += 1;
-    } else {
-        const T w = Pair<D, T>::weight(kv, acc.si, sj);
+    for (uint32_t k = b; k < e; ++k) {
+        T xj[3];
+        xj[0] = p(0, k);
+        if (xj[0] < xlo)
+            continue;
+        if (xj[0] > xhi)
+            break;
 #pragma unroll
-        for (int c = 0; c < NS; ++c) {
-            const M mj = static_cast<const M*>(a.m_mid[c])[j];
-            if (PREC == 2) {
-                // Kahan-compensated FP32 accumulation
-                const A y = static_cast<A>(w) * static_cast<A>(mj - acc.mi[c]) - acc.comp[c];
-                const A t = acc.dl[c] + y;
-                acc.comp[c] = (t - acc.dl[c]) - y;
-                acc.dl[c] = t;
-            } else {
-                acc.dl[c] += static_cast<A>(w) * static_cast<A>(mj - acc.mi[c]);
+        for (int d = 1; d < D; ++d)
+            xj[d] = p(d, k);
+        if (TRANSFER && k + jofs == i)
+            continue;
+        T r2;
+        if (!Pair<D, T>::inside(a, xi, xj, &r2))
+            continue;
+        const T kv = Pair<D, T>::kernel(a, r2);
+        if constexpr (!TRANSFER) {
+            acc.s += kv;
+            acc.cnt += 1;
+        } else {
+            const T w = Pair<D, T>::weight(kv, acc.si, sr(k));
+#pragma unroll
+            for (int c = 0; c < NS; ++c) {
+                const M mj = ms(c, k);
+                if (PREC == 2) {
+                    // Kahan-compensated FP32 accumulation
+                    const A y = static_cast<A>(w) * static_cast<A>(mj - acc.mi[c]) - acc.comp[c];
+                    const A t = acc.dl[c] + y;
+                    acc.comp[c] = (t - acc.dl[c]) - y;
+                    acc.dl[c] = t;
+                } else {
+                    acc.dl[c] += static_cast<A>(w) * static_cast<A>(mj - acc.mi[c]);
+                }
             }
         }
     }
 }
 
-// Candidates of one halo row segment: slots [gb, gb + len), staged at LDS
-// offset off when LDS is true.  Only the x-window [xlo, xhi] is visited.
-template <int D, int PREC, int NS, bool TRANSFER, bool LDS, int CAP>
-__device__ __forceinline__ void scan_row(const SimArgs& a, const typename Types<PREC>::T (&lpos)[D][CAP],
-                                         const typename Types<PREC>::T* lsr, uint32_t off, uint32_t len,
-                                         uint32_t gb, const typename Types<PREC>::T* xi,
-                                         typename Types<PREC>::T xlo, typename Types<PREC>::T xhi,
-                                         uint32_t i, Acc<PREC, NS, TRANSFER>& acc)
+// Walk, cell id and histogram slot of sorted particle i for the step after
+// a.step (the next step's binning, done while its position is in registers).
+template <int D, typename T>
+__device__ __forceinline__ void bin_next(const SimArgs& a, uint32_t i, const T* x)
 {
-    using T = typename Types<PREC>::T;
-    const T* gx0 = static_cast<const T*>(a.x[0]) + gb;
-    uint32_t lo = 0, hi = len;
-    while (lo < hi) {
-        const uint32_t mid = (lo + hi) >> 1;
-        const T v = LDS ? lpos[0][off + mid] : gx0[mid];
-        if (v < xlo)
-            lo = mid + 1;
-        else
-            hi = mid;
-    }
-    for (uint32_t k = lo; k < len; ++k) {
-        T xj[3];
-        xj[0] = LDS ? lpos[0][off + k] : gx0[k];
-        if (xj[0] > xhi)
-            break;
+    const uint32_t pid = a.pid_dst[i];
+    double z[3], spare;
+    normal_pair(a.seed, a.step + 1, pid, 0u, &z[0], &z[1]);
+    if (D == 3)
+        normal_pair(a.seed, a.step + 1, pid, 1u, &z[2], &spare);
+    uint32_t c = 0;
 #pragma unroll
-        for (int d = 1; d < D; ++d)
-            xj[d] = LDS ? lpos[d][off + k] : static_cast<const T*>(a.x[d])[gb + k];
-        T sj = T(0);
-        if (TRANSFER)
-            sj = LDS ? lsr[off + k] : static_cast<const T*>(a.srow)[gb + k];
-        visit<D, PREC, NS, TRANSFER>(a, xi, xj, sj, i, gb + k, acc);
+    for (int k = D - 1; k >= 0; --k) {
+        const T v = walk_reflect<T>(x[k], z[k], a.sdev, a.lo[k], a.hi[k], a.lof[k], a.hif[k]);
+        static_cast<T*>(a.xt[k])[i] = v;
+        c = c * static_cast<uint32_t>(a.nc[k]) +
+            static_cast<uint32_t>(cell_coord(static_cast<double>(v), a.glo[k], a.inv_side[k], a.nc[k]));
     }
+    a.cell[i] = c;
+    a.rank[i] = atomicAdd(&a.counts[c], 1u);
 }
 
+// One tile: tx * ty cells of plane tz.  Halo rows (cells xa..xb-1 of rows
+// y0-1..y1 of planes tz-1..tz+1) are staged in LDS with the offsets of their
+// cell boundaries; a particle in cell cx visits cells cx-1..cx+1 of each of
+// its 3^(d-1) neighbouring rows, restricted to the x-window.
 template <int D, int PREC, int NS, bool TRANSFER>
 __device__ __forceinline__ void tile_body(const SimArgs& a, uint32_t blk)
 {
     using T = typename Types<PREC>::T;
     using M = typename Types<PREC>::M;
-    constexpr int CAP = TileCap<D, T>::value;
+    constexpr int CAP = TileCap<D, PREC, NS, TRANSFER>::value;
     constexpr int planes = D == 3 ? 3 : 1;
+    constexpr int SCAP = TRANSFER ? CAP : 1;
     __shared__ T lpos[D][CAP];
-    __shared__ T lsr[TRANSFER ? CAP : 1];
-    __shared__ uint32_t seg_gb[kMaxSegs];
-    __shared__ uint32_t seg_off[kMaxSegs + 1];
-    __shared__ uint32_t own_gb[kMaxTileRows];
-    __shared__ uint32_t own_pre[kMaxTileRows + 1];
+    __shared__ T lsr[SCAP];
+    __shared__ M lms[NS][SCAP];
+    constexpr int kSegs = TileLimits<D>::segs;
+    constexpr int kRows = TileLimits<D>::max_y;
+    __shared__ uint32_t seg_gb[kSegs];
+    __shared__ uint32_t seg_off[kSegs + 1];
+    __shared__ uint32_t cst[kSegs][TileLimits<D>::cols];
+    __shared__ uint32_t own_gb[kRows];
+    __shared__ uint32_t own_pre[kRows + 1];
 
     const int tid = threadIdx.x;
     const int nc0 = a.nc[0], nc1 = a.nc[1], nc2 = a.nc[2];
@@ -515,8 +532,8 @@ __device__ __forceinline__ void tile_body(const SimArgs& a, uint32_t blk)
     const int nseg = rows * planes;
     const int xa = x0 > 0 ? x0 - 1 : 0;
     const int xb = x1 < nc0 ? x1 + 1 : nc0;
+    const int ncol = xb - xa;
 
-    // halo row segments: cells xa..xb-1 of rows y0-1..y1 (and planes tz-1..tz+1)
     uint32_t slen = 0;
     if (tid < nseg) {
         const int pz = D == 3 ? tz - 1 + tid / rows : 0;
@@ -535,7 +552,6 @@ __device__ __forceinline__ void tile_body(const SimArgs& a, uint32_t blk)
         seg_off[tid] = soff;
     if (tid == 0)
         seg_off[nseg] = total;
-    // own rows: cells x0..x1-1 of rows y0..y1-1 of plane tz
     uint32_t olen = 0;
     if (tid < nrow) {
         const uint32_t rb = (static_cast<uint32_t>(D == 3 ? tz : 0) * nc1 + (y0 + tid)) * nc0;
@@ -552,6 +568,21 @@ __device__ __forceinline__ void tile_body(const SimArgs& a, uint32_t blk)
     __syncthreads();
 
     const bool use_lds = total <= static_cast<uint32_t>(CAP);
+    // cell boundaries of every halo row, as LDS offsets (or global slots)
+    for (int idx = tid; idx < nseg * (ncol + 1); idx += kBlock) {
+        const int sg = idx / (ncol + 1);
+        const int c = idx - sg * (ncol + 1);
+        const int pz = D == 3 ? tz - 1 + sg / rows : 0;
+        const int py = y0 - 1 + sg % rows;
+        uint32_t v = use_lds ? seg_off[sg] : seg_gb[sg];
+        if (py >= 0 && py < nc1 && pz >= 0 && pz < nc2) {
+            const uint32_t rb = (static_cast<uint32_t>(pz) * nc1 + py) * nc0;
+            v = a.starts[rb + xa + c];
+            if (use_lds)
+                v = v - seg_gb[sg] + seg_off[sg];
+        }
+        cst[sg][c] = v;
+    }
     if (use_lds) {
         for (uint32_t idx = tid; idx < total; idx += kBlock) {
             int lo = 0, hi = nseg - 1;
@@ -566,8 +597,12 @@ __device__ __forceinline__ void tile_body(const SimArgs& a, uint32_t blk)
 #pragma unroll
             for (int d = 0; d < D; ++d)
                 lpos[d][idx] = static_cast<const T*>(a.x[d])[g];
-            if (TRANSFER)
+            if (TRANSFER) {
                 lsr[idx] = static_cast<const T*>(a.srow)[g];
+#pragma unroll
+                for (int c = 0; c < NS; ++c)
+                    lms[c][idx] = static_cast<const M*>(a.m_mid[c])[g];
+            }
         }
     }
     __syncthreads();
@@ -577,22 +612,28 @@ __device__ __forceinline__ void tile_body(const SimArgs& a, uint32_t blk)
 #pragma unroll
     for (int c = 0; c < NS; ++c)
         msum[c] = 0.0;
-    for (uint32_t t = tid; t < own_total; t += kBlock) {
+    // Every lane of the workgroup runs every pass of this loop (own_total is
+    // uniform), so the wave-wide maxima below see only live lanes.
+    for (uint32_t base = 0; base < own_total; base += kBlock) {
+        const uint32_t t = base + tid;
+        const bool act = t < own_total;
+        const uint32_t tt = act ? t : own_total - 1u;
         int r = 0, hi = nrow - 1;
         while (r < hi) {
             const int mid = (r + hi + 1) >> 1;
-            if (own_pre[mid] <= t)
+            if (own_pre[mid] <= tt)
                 r = mid;
             else
                 hi = mid - 1;
         }
-        const uint32_t i = own_gb[r] + (t - own_pre[r]);
+        const uint32_t i = own_gb[r] + (tt - own_pre[r]);
         T xi[3];
 #pragma unroll
         for (int d = 0; d < D; ++d)
             xi[d] = static_cast<const T*>(a.x[d])[i];
-        T xlo, xhi;
-        Window<T>::make(xi[0], a.win, &xlo, &xhi);
+        const int cxr = cell_coord(static_cast<double>(xi[0]), a.glo[0], a.inv_side[0], nc0) - xa;
+        const int cl = cxr > 0 ? cxr - 1 : 0;
+        const int ch = cxr + 2 < ncol ? cxr + 2 : ncol;
         Acc<PREC, NS, TRANSFER> acc;
         if constexpr (TRANSFER) {
             acc.si = static_cast<const T*>(a.srow)[i];
@@ -603,23 +644,79 @@ __device__ __forceinline__ void tile_body(const SimArgs& a, uint32_t blk)
                 acc.comp[c] = 0;
             }
         }
+        if (use_lds) {
+            // LDS slot of particle i itself (the self pair is skipped by slot)
+            const int smid = (planes == 3 ? rows : 0) + r + 1;
+            const uint32_t li = i - seg_gb[smid] + seg_off[smid];
 #pragma unroll
-        for (int pzr = 0; pzr < planes; ++pzr) {
+            for (int pzr = 0; pzr < planes; ++pzr) {
+                const int s0 = pzr * rows + r;
+                const uint32_t b0 = cst[s0][cl], l0 = cst[s0][ch] - b0;
+                const uint32_t b1 = cst[s0 + 1][cl], l1 = cst[s0 + 1][ch] - b1;
+                const uint32_t b2 = cst[s0 + 2][cl], l2 = cst[s0 + 2][ch] - b2;
+                const uint32_t tot = act ? l0 + l1 + l2 : 0u;
+                const uint32_t o1 = b1 - l0, o2 = b2 - l0 - l1;
+                uint32_t kmax = tot;
 #pragma unroll
-            for (int dy = 0; dy < 3; ++dy) {
-                const int s = pzr * rows + r + dy;
-                const uint32_t off = seg_off[s];
-                const uint32_t len = seg_off[s + 1] - off;
-                if (len == 0)
-                    continue;
-                if (use_lds)
-                    scan_row<D, PREC, NS, TRANSFER, true, CAP>(a, lpos, lsr, off, len, seg_gb[s], xi, xlo,
-                                                               xhi, i, acc);
-                else
-                    scan_row<D, PREC, NS, TRANSFER, false, CAP>(a, lpos, lsr, off, len, seg_gb[s], xi,
-                                                                xlo, xhi, i, acc);
+                for (int off = 32; off >= 1; off >>= 1)
+                    kmax = max(kmax, static_cast<uint32_t>(__shfl_xor(static_cast<int>(kmax), off, 64)));
+                kmax = __builtin_amdgcn_readfirstlane(kmax);
+                for (uint32_t k = 0; k < kmax; ++k) {
+                    const bool valid = k < tot;
+                    uint32_t idx = k + (k < l0 ? b0 : (k < l0 + l1 ? o1 : o2));
+                    idx = valid ? idx : li;
+                    T xj[3];
+#pragma unroll
+                    for (int d = 0; d < D; ++d)
+                        xj[d] = lpos[d][idx];
+                    T r2;
+                    bool in = Pair<D, T>::inside(a, xi, xj, &r2) && valid;
+                    if (TRANSFER)
+                        in = in && idx != li;
+                    const T kv = Pair<D, T>::kernel(a, r2);
+                    if constexpr (!TRANSFER) {
+                        acc.s += in ? kv : T(0);
+                        acc.cnt += in ? 1u : 0u;
+                    } else {
+                        using A = typename Types<PREC>::A;
+                        const T w = Pair<D, T>::weight(kv, acc.si, lsr[idx]);
+#pragma unroll
+                        for (int c = 0; c < NS; ++c) {
+                            const M mj = lms[c][idx];
+                            if (PREC == 2) {
+                                const A y = static_cast<A>(w) * static_cast<A>(mj - acc.mi[c]) - acc.comp[c];
+                                const A tk = acc.dl[c] + y;
+                                const A cn = (tk - acc.dl[c]) - y;
+                                acc.comp[c] = in ? cn : acc.comp[c];
+                                acc.dl[c] = in ? tk : acc.dl[c];
+                            } else {
+                                const A d = static_cast<A>(w) * static_cast<A>(mj - acc.mi[c]);
+                                acc.dl[c] += in ? d : A(0);
+                            }
+                        }
+                    }
+                }
+            }
+        } else {
+#pragma unroll
+            for (int pzr = 0; pzr < planes; ++pzr) {
+#pragma unroll
+                for (int dy = 0; dy < 3; ++dy) {
+                    const int sg = pzr * rows + r + dy;
+                    const uint32_t b = cst[sg][cl];
+                    const uint32_t e = act ? cst[sg][ch] : b;
+                    T xlo, xhi;
+                    Window<T>::make(xi[0], a.win, &xlo, &xhi);
+                    scan_row<D, PREC, NS, TRANSFER>(
+                        a, [&](int d, uint32_t k) { return static_cast<const T*>(a.x[d])[k]; },
+                        [&](uint32_t k) { return static_cast<const T*>(a.srow)[k]; },
+                        [&](int c, uint32_t k) { return static_cast<const M*>(a.m_mid[c])[k]; }, b, e, 0u, xi,
+                        xlo, xhi, i, acc);
+                }
             }
         }
+        if (!act)
+            continue;
         if constexpr (!TRANSFER) {
             static_cast<T*>(a.srow)[i] = acc.s;
             pairs += acc.cnt - 1u;
@@ -642,6 +739,8 @@ __device__ __forceinline__ void tile_body(const SimArgs& a, uint32_t blk)
                 static_cast<M*>(a.m_dst[c])[i] = st;
                 msum[c] += static_cast<double>(st);
             }
+            if (a.fuse_bin)
+                bin_next<D, T>(a, i, xi);
         }
     }
     if constexpr (!TRANSFER) {
@@ -915,11 +1014,13 @@ const char* phase_name(int ph)
     return (ph >= 0 && ph < PH_COUNT) ? names[ph] : "?";
 }
 
-int tile_capacity(int dim, int prec)
+int tile_capacity(int dim, int prec, int ns)
 {
+#define MTPT_CAP(D, P) (ns == 3 ? TileCap<D, P, 3, true>::value : TileCap<D, P, 1, true>::value)
     if (dim == 2)
-        return prec == 0 ? TileCap<2, double>::value : TileCap<2, float>::value;
-    return prec == 0 ? TileCap<3, double>::value : TileCap<3, float>::value;
+        return prec == 0 ? MTPT_CAP(2, 0) : prec == 1 ? MTPT_CAP(2, 1) : MTPT_CAP(2, 2);
+    return prec == 0 ? MTPT_CAP(3, 0) : prec == 1 ? MTPT_CAP(3, 1) : MTPT_CAP(3, 2);
+#undef MTPT_CAP
 }
 
 static uint32_t ceil_div(int64_t a, int64_t b) { return static_cast<uint32_t>((a + b - 1) / b); }

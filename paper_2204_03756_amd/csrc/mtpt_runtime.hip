@@ -170,11 +170,11 @@ Plan make_plan(const mtpt_params& p)
     {
         const double rho_c = static_cast<double>(q.n) / static_cast<double>(q.ncells);
         const int planes = q.dim == 3 ? 3 : 1;
-        const double cap = static_cast<double>(tile_capacity(q.dim, q.prec)) / 1.6;
-        const double cells_own = std::max(1.0, 224.0 / std::max(rho_c, 1e-9));
+        const double cap = static_cast<double>(tile_capacity(q.dim, q.prec, q.ns)) / 1.6;
+        const double cells_own = std::max(1.0, 640.0 / std::max(rho_c, 1e-9));
         int t = static_cast<int>(std::lround(std::sqrt(cells_own)));
-        int tx = std::max(1, std::min(t, std::min(q.nc[0], 4096)));
-        int ty = std::max(1, std::min(t, std::min(q.nc[1], kMaxTileRows)));
+        int tx = std::max(1, std::min(t, std::min(q.nc[0], tile_max(q.dim))));
+        int ty = std::max(1, std::min(t, std::min(q.nc[1], tile_max(q.dim))));
         while ((tx + 2.0) * (ty + 2.0) * planes * rho_c > cap && (tx > 1 || ty > 1)) {
             if (tx >= ty)
                 --tx;
@@ -245,6 +245,7 @@ struct mtpt_sim {
     int64_t steps_done = 0;   // steps enqueued since create
     bool moving = false;
     bool s_valid = false;
+    bool bin_ready = false;   // the last transfer already binned for this step
     double mass_initial[3]{};
     // profiling
     bool profiling = false;
@@ -315,6 +316,7 @@ SimArgs base_args(const mtpt_sim* s)
     a.psi2_out = static_cast<float>(a.psi2 * (1.0 + 1e-5));
     a.kc = p.beta / (4.0 * p.d_mt * p.dt);
     a.kcf = static_cast<float>(a.kc);
+    a.kcf2 = static_cast<float>(-a.kc * 1.4426950408889634);
     a.beta = p.beta;
     a.betaf = static_cast<float>(p.beta);
     a.k_react = p.k_react;
@@ -376,6 +378,7 @@ SimArgs step_args(const mtpt_sim* s, bool* rowsum_needed)
         }
         a.recompute_s = s->s_valid ? 0 : 1;
     }
+    a.fuse_bin = s->moving ? 1 : 0;
     *rowsum_needed = a.recompute_s != 0;
     return a;
 }
@@ -396,11 +399,15 @@ int launch(mtpt_sim* s, int ph, const SimArgs& a)
     return MTPT_OK;
 }
 
-int enqueue_binning(mtpt_sim* s, const SimArgs& a)
+// Binning; the bin phase itself is skipped when the previous transfer pass
+// already walked and binned every particle for this step.
+int enqueue_binning(mtpt_sim* s, const SimArgs& a, bool with_bin)
 {
     static const int phases[] = {PH_BIN, PH_SCAN_REDUCE, PH_SCAN_TOP, PH_SCAN_DOWN,
                                  PH_SCATTER, PH_PLACE};
     for (int ph : phases) {
+        if (ph == PH_BIN && !with_bin)
+            continue;
         const int rc = launch(s, ph, a);
         if (rc)
             return rc;
@@ -413,7 +420,7 @@ int enqueue_step(mtpt_sim* s)
     bool need_rowsum = false;
     SimArgs a = step_args(s, &need_rowsum);
     if (s->moving) {
-        const int rc = enqueue_binning(s, a);
+        const int rc = enqueue_binning(s, a, !s->bin_ready);
         if (rc)
             return rc;
     }
@@ -431,6 +438,8 @@ int enqueue_step(mtpt_sim* s)
     s->steps_done += 1;
     if (!s->moving)
         s->s_valid = true;
+    else
+        s->bin_ready = true;
     return MTPT_OK;
 }
 
@@ -518,7 +527,7 @@ int create_into(mtpt_sim* s, const double* pos, const double* mass)
             a.m_mid[c] = s->M[0][c];
             a.m_dst[c] = s->M[0][c];
         }
-        const int rc = enqueue_binning(s, a);
+        const int rc = enqueue_binning(s, a, true);
         if (rc)
             return rc;
         HIP_TRY(launch_totals(q.prec, a, s->M[0], s->stream));
@@ -906,14 +915,15 @@ int ring_reserve(mtpt_pool* p, RingSlot& r, size_t bytes)
 }
 
 struct GroupKey {
-    int dim, prec, ns, moving, rowsum;
+    int dim, prec, ns, moving, rowsum, bin;
     bool operator<(const GroupKey& o) const
     {
         if (dim != o.dim) return dim < o.dim;
         if (prec != o.prec) return prec < o.prec;
         if (ns != o.ns) return ns < o.ns;
         if (moving != o.moving) return moving < o.moving;
-        return rowsum < o.rowsum;
+        if (rowsum != o.rowsum) return rowsum < o.rowsum;
+        return bin < o.bin;
     }
 };
 
@@ -998,7 +1008,8 @@ int mtpt_pool_tick(mtpt_pool* p, int32_t* n_completed)
         mtpt_sim* s = kv.second;
         if (s->steps_done >= s->steps_target || s->q.n == 0)
             continue;
-        const GroupKey k{s->q.dim, s->q.prec, s->q.ns, s->moving ? 1 : 0, (s->moving || !s->s_valid) ? 1 : 0};
+        const GroupKey k{s->q.dim, s->q.prec, s->q.ns, s->moving ? 1 : 0, (s->moving || !s->s_valid) ? 1 : 0,
+                         (s->moving && !s->bin_ready) ? 1 : 0};
         groups[k].push_back(s);
     }
     // layout of the argument block: per group, SimArgs[ns] then PH_COUNT
@@ -1045,8 +1056,11 @@ int mtpt_pool_tick(mtpt_pool* p, int32_t* n_completed)
             const uint32_t* dpre = reinterpret_cast<const uint32_t*>(d + align_up(goff[gi] + ns * sizeof(SimArgs), 256));
             const uint32_t* hpre = reinterpret_cast<const uint32_t*>(h + align_up(goff[gi] + ns * sizeof(SimArgs), 256));
             std::vector<int> phases;
+            if (k.bin)
+                phases.push_back(PH_BIN);
             if (k.moving)
-                phases = {PH_BIN, PH_SCAN_REDUCE, PH_SCAN_TOP, PH_SCAN_DOWN, PH_SCATTER, PH_PLACE};
+                for (int ph : {PH_SCAN_REDUCE, PH_SCAN_TOP, PH_SCAN_DOWN, PH_SCATTER, PH_PLACE})
+                    phases.push_back(ph);
             if (k.rowsum)
                 phases.push_back(PH_ROWSUM);
             phases.push_back(PH_TRANSFER);
@@ -1063,6 +1077,8 @@ int mtpt_pool_tick(mtpt_pool* p, int32_t* n_completed)
                 s->steps_done += 1;
                 if (!s->moving)
                     s->s_valid = true;
+                else
+                    s->bin_ready = true;
                 if (s->steps_done == s->steps_target)
                     ++completed;
             }
