@@ -29,13 +29,15 @@ def algorithmic_bytes(kernel: str, n: int, dim: int, ns: int, tsz: int, msz: int
     """Bytes each launch must move at minimum (one read of every input it
     needs, one write of every output), per the data layout of the path."""
     pos = dim * tsz
+    walk = 4 + pos + 4 + 4                         # pid in; walked x, cell, slot out
     per = {
-        "bin": pos + 4 + pos + 4 + 4,             # x, pid in; xt, cell, rank out
+        "bin": pos + walk,                         # x in + the walk
         "scatter": 4 + 4 + 4,                      # cell, rank in; perm out
-        "cellsort": 4 + 4,                         # perm in/out (+ pid keys)
-        "gather": 4 + pos + ns * msz + 4 + pos + ns * msz + 4,
+        # perm, cell, x, m, pid of the slot's particle in; x, m, pid out
+        "place": 4 + 4 + pos + ns * msz + 4 + pos + ns * msz + 4,
         "rowsum": pos + tsz,                       # x in; s out
-        "transfer": pos + tsz + ns * msz + ns * msz,  # x, s, m in; m out
+        # x, s, m in; m out; then the next step's walk of the same particle
+        "transfer": pos + tsz + ns * msz + ns * msz + walk,
     }
     if kernel in ("scan_reduce",):
         return ncells * 4.0
@@ -44,13 +46,17 @@ def algorithmic_bytes(kernel: str, n: int, dim: int, ns: int, tsz: int, msz: int
     return float(per.get(kernel, 0) * n)
 
 
-def run_path(mt, W, precision: int, steps: int, warmup: int, profile_steps: int = 5):
+def run_path(mt, W, precision: int, steps: int, warmup: int, profile_steps: int = 5,
+             workload: str = "rw2d"):
     import torch
-    w = W.rw2d(precision=precision, steps=steps)
+    w = W.make(workload, precision=precision, steps=steps)
     stream = torch.cuda.Stream()
     alloc = mt.TorchAllocator("cuda:0")
     with torch.cuda.stream(stream):
+        tc0 = time.perf_counter()
         sim = mt.Sim(w.params, w.x0, w.m0, allocator=alloc, stream=int(stream.cuda_stream))
+        torch.cuda.synchronize()
+        create_s = time.perf_counter() - tc0
         sim.step(warmup)
         torch.cuda.synchronize()
         st0 = sim.stats()
@@ -79,7 +85,7 @@ def run_path(mt, W, precision: int, steps: int, warmup: int, profile_steps: int 
         "p50_ms": per_step[len(per_step) // 2],
         "p99_ms": per_step[min(len(per_step) - 1, int(math.ceil(0.99 * len(per_step))) - 1)],
         "phases": phases, "n_cells": st1["n_cells"], "drift": st1["drift"],
-        "pairs_per_step": st1["pairs_last"],
+        "pairs_per_step": st1["pairs_last"], "create_s": create_s,
     }
 
 
@@ -98,6 +104,42 @@ def roofline(res, dim, ns, tsz, msz, n):
             "phase_ms_per_step": {k: round(v[0] / v[1], 4) for k, v in phases.items()}}
 
 
+def traffic_from_profile(kernel: str, workload: str, precision: str):
+    """HBM bytes per launch of a kernel from the committed PMC summary, or
+    None when the kernel source changed since the counters were taken."""
+    import hashlib
+    src = os.path.join(ROOT, "paper_2204_03756_amd", "csrc", "mtpt_kernels.hip")
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}_{precision}.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    k = rec.get("kernels", {}).get(kernel)
+    if rec.get("source_sha256") != sha or k is None:
+        return None
+    return k["bytes_per_launch"]
+
+
+def profile_driver(mt, W, workload: str, precision: int, steps: int):
+    """Target of the PMC runs: a calibration copy of a known size, then a few
+    steps of one workload.  Prints nothing but its own markers."""
+    import torch
+    n = 64 * 1024 * 1024                           # 256 MiB of float32
+    x = torch.ones(n, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(f"calibration copy: {4 * n} bytes read and written per launch", flush=True)
+    w = W.make(workload, precision=precision, steps=steps)
+    sim = mt.Sim(w.params, w.x0, w.m0, allocator=mt.TorchAllocator("cuda:0"))
+    sim.step(steps)
+    st = sim.stats()
+    sim.close()
+    print(f"profiled {workload} precision {precision}: {steps} steps, pairs/step {st['pairs_last']}",
+          flush=True)
+
+
 def cpu_baseline(W, seconds_hint: float = 20.0):
     """The oracle on the host cores, on a bounded sample: the first steps of
     the same 4e6-particle workload (FP32 position state, as the timed path)."""
@@ -114,6 +156,40 @@ def cpu_baseline(W, seconds_hint: float = 20.0):
                       f"{int(r.pairs.sum())} pair-updates in {dt:.1f} s"}
 
 
+def serve_bench(mt, W, n_req: int, seed: int = 20220404):
+    """The serving mix: closed-loop capacity first (all requests at t = 0),
+    then a Poisson stream at 80 % of that capacity, both through the pool."""
+    from paper_2204_03756_amd import serve
+    import torch
+    alloc = mt.TorchAllocator("cuda:0")
+    reqs = [W.request(i, base_seed=seed) for i in range(n_req)]
+    be = serve.PoolBackend(0, 64, allocator=alloc)
+    try:
+        closed = serve.serve(be, reqs, None, realtime=True).summary()
+    finally:
+        be.close()
+    torch.cuda.synchronize()
+    rate = 0.8 * closed["sims_per_s"]
+    reqs2 = [W.request(n_req + i, base_seed=seed) for i in range(n_req)]
+    arr = W.arrivals(n_req, rate, seed=seed + 1)
+    be = serve.PoolBackend(0, 64, allocator=alloc)
+    try:
+        open_ = serve.serve(be, reqs2, arr, realtime=True).summary()
+    finally:
+        be.close()
+    return closed, open_, rate
+
+
+WORKLOAD_TEXT = {
+    "rw2d": "rw2d: 2-d MTPT with random walk, N=4e6 in [0,2000]^2, D_RW=D_MT=0.5, dt=0.1, "
+            "psi=3*sqrt(4*D_MT*dt), 100 steps, Gaussian blob sigma 50",
+    "rw3d": "rw3d: 3-d MTPT with random walk, N=2e6 in [0,126]^3, D_RW=D_MT=1, dt=0.1, "
+            "psi=3*sqrt(4*D_MT*dt), 100 steps, 1000-particle central source",
+    "react3d": "react3d: 3-d MTPT, N=3.2e7 in [0,318]^3, D_RW=0.3, D_MT=0.7, dt=0.05, 200 steps, "
+               "A+B->C mass-based reaction after each transfer, k=1",
+}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -121,6 +197,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--workload", default="rw2d", choices=["rw2d", "rw3d", "react3d", "serve"],
+                    help="rw2d is the benchmark line; the others are reported the same way")
+    ap.add_argument("--requests", type=int, default=120, help="serving mix size")
+    ap.add_argument("--profile-driver", action="store_true",
+                    help="run a calibration copy and a few steps (for rocprofv3 --pmc)")
+    ap.add_argument("--precision", default="fp32w", choices=["fp64", "fp32w", "kahan"])
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the MTPT path here is single-GPU "
@@ -133,7 +215,24 @@ def main():
     mt = mtpt
     mt.load()
 
-    r32 = run_path(mt, W, W.FP32W_FP64ACC, args.steps, args.warmup)
+    if args.profile_driver:
+        profile_driver(mt, W, args.workload, W.PRECISIONS[args.precision], args.steps)
+        return
+
+    if args.workload == "serve":
+        closed, open_, rate = serve_bench(mt, W, args.requests)
+        print(json.dumps({
+            "metric": "serving mix: sims/s and p50/p99 request latency (continuous batching)",
+            "value": open_["sims_per_s"], "unit": "sims/s", "n_gpus": 1,
+            "higher_is_better": True, "dtype": "f32-kahan", "data": "synthetic",
+            "config": {"workload": "serve: independent 2-d/3-d sims, N log-uniform in [1e4,1e6], "
+                                   "density 1, D in {0.5,1,2}, 20-200 steps, Kahan FP32",
+                       "requests": args.requests, "poisson_rate_per_s": rate},
+            "closed_loop": closed, "poisson": open_}), flush=True)
+        return
+
+    workload = args.workload
+    r32 = run_path(mt, W, W.FP32W_FP64ACC, args.steps, args.warmup, workload=workload)
     w = r32["w"]
     p = w.params
     out = {
@@ -142,22 +241,31 @@ def main():
         "warmup": args.warmup, "ms_per_step": r32["ms_per_step"], "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32-weights/f64-accum",
         "data": "synthetic (seeded uniform positions, Gaussian mass blob)",
-        "config": {"workload": "rw2d: 2-d MTPT with random walk, N=4e6 in [0,2000]^2, D_RW=D_MT=0.5, "
-                               "dt=0.1, psi=3*sqrt(4*D_MT*dt), 100 steps, Gaussian blob sigma 50",
-                   "n": p.n, "dim": 2, "precision": "fp32w_fp64acc",
+        "config": {"workload": WORKLOAD_TEXT[workload],
+                   "n": p.n, "dim": p.dim, "precision": "fp32w_fp64acc",
                    "pairs_per_step": r32["pairs_per_step"], "n_cells": r32["n_cells"]},
+        "create_s_pcie_inclusive": r32["create_s"],
         "p50_step_ms": r32["p50_ms"], "p99_step_ms": r32["p99_ms"],
         "mass_drift": r32["drift"],
     }
-    out["roofline"] = roofline(r32, 2, 1, 4, 8, p.n)
+    ns = p.n_species
+    out["roofline"] = roofline(r32, p.dim, ns, 4, 8, p.n)
+    if out["roofline"]:
+        t = traffic_from_profile(out["roofline"]["kernel"], workload, "fp32w")
+        out["roofline"]["traffic"] = t
+    if workload == "rw3d":
+        rk = run_path(mt, W, W.FP32_KAHAN, args.steps, args.warmup, workload=workload)
+        out["kahan_path"] = {"value": rk["value"], "ms_per_step": rk["ms_per_step"],
+                             "p50_step_ms": rk["p50_ms"], "p99_step_ms": rk["p99_ms"],
+                             "mass_drift": rk["drift"], "roofline": roofline(rk, p.dim, ns, 4, 4, p.n)}
     if not args.no_fp64:
-        r64 = run_path(mt, W, W.FP64, args.steps, args.warmup)
+        r64 = run_path(mt, W, W.FP64, args.steps, args.warmup, workload=workload)
         out["fp64_path"] = {"value": r64["value"], "ms_per_step": r64["ms_per_step"],
                             "p50_step_ms": r64["p50_ms"], "p99_step_ms": r64["p99_ms"],
                             "mass_drift": r64["drift"],
-                            "roofline": roofline(r64, 2, 1, 8, 8, p.n)}
+                            "roofline": roofline(r64, p.dim, ns, 8, 8, p.n)}
         out["fp32_over_fp64"] = r32["value"] / r64["value"]
-    if not args.no_cpu:
+    if not args.no_cpu and workload == "rw2d":
         out["cpu_baseline"] = cpu_baseline(W)
     print(json.dumps(out), flush=True)
 

@@ -173,6 +173,9 @@ int mtpt_pool_tick(mtpt_pool* pool, int32_t* n_completed);
 /* 1 in *done if the ticket's sim has taken all its steps (synchronises). */
 int mtpt_pool_done(mtpt_pool* pool, int64_t ticket, int32_t* done);
 
+/* Counters and totals of an admitted sim (see mtpt_stats_t).  Synchronises. */
+int mtpt_pool_stats(mtpt_pool* pool, int64_t ticket, mtpt_stats_t* out);
+
 /* Copy a finished sim's masses (FP64 [n_species][n], original order) and
  * free its slot and memory.  Synchronises.  MTPT_E_STATE if not finished. */
 int mtpt_pool_result(mtpt_pool* pool, int64_t ticket, double* mass_out);

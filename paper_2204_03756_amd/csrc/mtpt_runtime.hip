@@ -1109,6 +1109,16 @@ int mtpt_pool_done(mtpt_pool* p, int64_t ticket, int32_t* done)
     return MTPT_OK;
 }
 
+int mtpt_pool_stats(mtpt_pool* p, int64_t ticket, mtpt_stats_t* out)
+{
+    if (!p || !out)
+        return fail(MTPT_E_ARG, "NULL argument");
+    auto it = p->sims.find(ticket);
+    if (it == p->sims.end())
+        return fail(MTPT_E_ARG, "unknown ticket %lld", (long long)ticket);
+    return mtpt_stats(it->second, out);
+}
+
 int mtpt_pool_result(mtpt_pool* p, int64_t ticket, double* mass_out)
 {
     if (!p)

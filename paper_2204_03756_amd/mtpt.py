@@ -96,6 +96,7 @@ def load():
         "mtpt_pool_tick": (C.c_int, [C.c_void_p, P(C.c_int32)]),
         "mtpt_pool_done": (C.c_int, [C.c_void_p, C.c_int64, P(C.c_int32)]),
         "mtpt_pool_result": (C.c_int, [C.c_void_p, C.c_int64, _f64p]),
+        "mtpt_pool_stats": (C.c_int, [C.c_void_p, C.c_int64, P(mtpt_stats_t)]),
         "mtpt_pool_usage": (C.c_int, [C.c_void_p, P(C.c_int32), P(C.c_size_t), P(C.c_size_t)]),
         "mtpt_sim_bytes": (C.c_int, [P(mtpt_params), P(C.c_size_t)]),
         "mtpt_pool_destroy": (C.c_int, [C.c_void_p]),
@@ -201,14 +202,24 @@ def mtpt_positions(sim, n: int, dim: int) -> np.ndarray:
     return out
 
 
-def mtpt_stats(sim) -> dict:
-    st = mtpt_stats_t()
-    _check(load().mtpt_stats(sim, C.byref(st)))
+def _stats_dict(st) -> dict:
     return {
         "steps_done": st.steps_done, "pairs_last": st.pairs_last, "pairs_total": st.pairs_total,
         "mass_total": list(st.mass_total), "mass_initial": list(st.mass_initial),
         "drift": st.drift, "nonfinite": st.nonfinite, "n_cells": st.n_cells,
     }
+
+
+def mtpt_stats(sim) -> dict:
+    st = mtpt_stats_t()
+    _check(load().mtpt_stats(sim, C.byref(st)))
+    return _stats_dict(st)
+
+
+def mtpt_pool_stats(pool, ticket: int) -> dict:
+    st = mtpt_stats_t()
+    _check(load().mtpt_pool_stats(pool, int(ticket), C.byref(st)))
+    return _stats_dict(st)
 
 
 def mtpt_neighbors(sim, n: int):
