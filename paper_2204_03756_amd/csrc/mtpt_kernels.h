@@ -27,7 +27,9 @@ constexpr int kBlock = 256;          // threads per workgroup, 4 wave64s
 constexpr int kScanItems = 16;       // counts per thread in the scan
 constexpr int kScanTile = kBlock * kScanItems;
 constexpr int kFinalBlock = 1024;    // threads of the finalize kernel
-constexpr int kLdsBudget = 24576;    // bytes of staged particle data per workgroup
+// bytes of staged particle data per workgroup of the mass-transfer passes
+// (3-d halos hold three planes of cell rows)
+template <int D> struct LdsBudget { static constexpr int value = D == 2 ? 24576 : 46080; };
 
 // Largest tile (cells in x and in y) of the mass-transfer passes, the halo
 // cell rows it spans and the cell boundaries kept per halo row.
@@ -73,6 +75,11 @@ struct SimArgs {
     double psi;
     double psi2;             // psi * psi (FP64, the canonical cutoff)
     double win;              // x-window half width, psi (1 + 1e-6)
+    double side[3];          // cell side per dimension
+    double win2d;            // win * win
+    float win2f;
+    float wmarginf;          // rounding margin of row windows (FP32 positions)
+    double wmargind;         // the same for FP64 positions
     float psi2_in;           // FP32 r^2 below this: inside for sure
     float psi2_out;          // FP32 r^2 above this: outside for sure
     double kc;
@@ -105,7 +112,7 @@ struct SimArgs {
     int32_t recompute_s;     // the row-sum pass ran this step
     int32_t walk;            // apply the jump in the bin pass (0 at create)
     int32_t fuse_bin;        // the transfer pass also bins for the next step
-    int32_t pad1;
+    int32_t trim_rows;       // trim candidate rows to the per-row x-window
 };
 
 // Batched launches: a device array of SimArgs and a device prefix of blocks

@@ -34,13 +34,13 @@ template <> struct Types<1> { using T = float;  using M = double; using A = doub
 template <> struct Types<2> { using T = float;  using M = float;  using A = float;  };
 
 // particles staged per workgroup (tile cells plus halo): positions, and for
-// the transfer pass also row sums and masses, within kLdsBudget bytes
+// the transfer pass also row sums and masses, within the LDS budget
 template <int D, int PREC, int NS, bool TRANSFER> struct TileCap {
     using T = typename Types<PREC>::T;
     using M = typename Types<PREC>::M;
     static constexpr int bytes =
         D * static_cast<int>(sizeof(T)) + (TRANSFER ? static_cast<int>(sizeof(T) + NS * sizeof(M)) : 0);
-    static constexpr int value = kLdsBudget / bytes;
+    static constexpr int value = LdsBudget<D>::value / bytes;
 };
 
 __device__ __forceinline__ int cell_coord(double x, double glo, double inv, int nc)
@@ -248,6 +248,19 @@ __device__ __forceinline__ V block_sum(V v)
     return t;
 }
 
+// Workgroups are dispatched to the 8 XCDs round-robin (workgroup b on XCD
+// b mod 8), each XCD with its own L2.  Remapping b so that every XCD runs one
+// contiguous chunk of logical blocks keeps neighbouring tiles and slot ranges,
+// which share halo rows and gather sources, in the same L2.  The map is a
+// bijection of [0, n) whatever the dispatch order.
+__device__ __forceinline__ uint32_t xcd_block(uint32_t b, uint32_t n)
+{
+    constexpr uint32_t kXcd = 8;
+    const uint32_t per = n / kXcd, rem = n % kXcd;
+    const uint32_t x = b % kXcd, k = b / kXcd;
+    return x * per + (x < rem ? x : rem) + k;
+}
+
 // -------------------------------------------------------------- binning
 template <int D, typename T>
 __device__ __forceinline__ void bin_body(const SimArgs& a, uint32_t blk)
@@ -401,6 +414,17 @@ __device__ __forceinline__ void react3(double* m, const SimArgs& a)
     m[1] = (sw ? an : bn) * a.to_m;
     m[2] = m[2] + reacted * a.to_m;
 }
+
+// Rows are trimmed to the particle's x-window (per row, from its y/z
+// distance) before the candidate loop when rows are long (a.trim_rows, set
+// by the host from the mean cell occupancy); short rows are scanned whole.
+
+template <typename T> __device__ __forceinline__ T win2_of(const SimArgs& a);
+template <> __device__ __forceinline__ double win2_of<double>(const SimArgs& a) { return a.win2d; }
+template <> __device__ __forceinline__ float win2_of<float>(const SimArgs& a) { return a.win2f; }
+template <typename T> __device__ __forceinline__ T wmargin_of(const SimArgs& a);
+template <> __device__ __forceinline__ double wmargin_of<double>(const SimArgs& a) { return a.wmargind; }
+template <> __device__ __forceinline__ float wmargin_of<float>(const SimArgs& a) { return a.wmarginf; }
 
 // Per-particle accumulator of the two passes.
 template <int PREC, int NS, bool TRANSFER> struct Acc;
@@ -648,12 +672,73 @@ __device__ __forceinline__ void tile_body(const SimArgs& a, uint32_t blk)
             // LDS slot of particle i itself (the self pair is skipped by slot)
             const int smid = (planes == 3 ? rows : 0) + r + 1;
             const uint32_t li = i - seg_gb[smid] + seg_off[smid];
+            // distances from the particle to the y (and z) slabs of the rows
+            // below and above its own, less a rounding margin
+            const int cyc = cell_coord(static_cast<double>(xi[1]), a.glo[1], a.inv_side[1], nc1);
+            const T ylo = static_cast<T>(a.glo[1] + cyc * a.side[1]);
+            const T dyv[3] = {xi[1] - ylo - wmargin_of<T>(a), T(0), ylo + static_cast<T>(a.side[1]) - xi[1] - wmargin_of<T>(a)};
+            T dzv[3] = {T(0), T(0), T(0)};
+            if (D == 3) {
+                const int czc = cell_coord(static_cast<double>(xi[2]), a.glo[2], a.inv_side[2], nc2);
+                const T zlo = static_cast<T>(a.glo[2] + czc * a.side[2]);
+                dzv[0] = xi[2] - zlo - wmargin_of<T>(a);
+                dzv[2] = zlo + static_cast<T>(a.side[2]) - xi[2] - wmargin_of<T>(a);
+            }
 #pragma unroll
             for (int pzr = 0; pzr < planes; ++pzr) {
                 const int s0 = pzr * rows + r;
-                const uint32_t b0 = cst[s0][cl], l0 = cst[s0][ch] - b0;
-                const uint32_t b1 = cst[s0 + 1][cl], l1 = cst[s0 + 1][ch] - b1;
-                const uint32_t b2 = cst[s0 + 2][cl], l2 = cst[s0 + 2][ch] - b2;
+                uint32_t b0 = cst[s0][cl], l0 = cst[s0][ch] - b0;
+                uint32_t b1 = cst[s0 + 1][cl], l1 = cst[s0 + 1][ch] - b1;
+                uint32_t b2 = cst[s0 + 2][cl], l2 = cst[s0 + 2][ch] - b2;
+                if (a.trim_rows) {
+                    // x-window of each row from its y/z distance: |dx|^2 <= psi^2 - dy^2 - dz^2
+                    const T dz = dzv[D == 3 ? pzr : 1] > T(0) ? dzv[D == 3 ? pzr : 1] : T(0);
+                    uint32_t bb[3] = {b0, b1, b2}, ll[3] = {l0, l1, l2};
+                    T wlo[3], whi[3];
+                    uint32_t lmax = 0;
+#pragma unroll
+                    for (int q = 0; q < 3; ++q) {
+                        const T dy = dyv[q] > T(0) ? dyv[q] : T(0);
+                        const T w2 = win2_of<T>(a) - dy * dy - dz * dz;
+                        const T w = w2 > T(0) ? static_cast<T>(sqrt(w2)) + wmargin_of<T>(a) : T(0);
+                        wlo[q] = xi[0] - w;
+                        whi[q] = xi[0] + w;
+                        if (!(w2 > T(0)))
+                            ll[q] = 0;
+                        lmax = max(lmax, ll[q]);
+                    }
+#pragma unroll
+                    for (int off = 32; off >= 1; off >>= 1)
+                        lmax = max(lmax, static_cast<uint32_t>(__shfl_xor(static_cast<int>(lmax), off, 64)));
+                    lmax = __builtin_amdgcn_readfirstlane(lmax);
+                    const int nsteps = 32 - __builtin_clz(lmax | 1u);
+#pragma unroll
+                    for (int q = 0; q < 3; ++q) {
+                        // first slot with x >= wlo, then first with x > whi
+                        uint32_t lo = bb[q], n = ll[q];
+                        for (int st = 0; st < nsteps; ++st) {
+                            const uint32_t half = n >> 1;
+                            const uint32_t mid = lo + half;
+                            const bool go = n > 0u && lpos[0][mid < CAP ? mid : CAP - 1] < wlo[q];
+                            lo = go ? mid + 1u : lo;
+                            n = go ? n - half - 1u : half;
+                        }
+                        uint32_t hi = lo;
+                        n = bb[q] + ll[q] - lo;
+                        for (int st = 0; st < nsteps; ++st) {
+                            const uint32_t half = n >> 1;
+                            const uint32_t mid = hi + half;
+                            const bool go = n > 0u && !(lpos[0][mid < CAP ? mid : CAP - 1] > whi[q]);
+                            hi = go ? mid + 1u : hi;
+                            n = go ? n - half - 1u : half;
+                        }
+                        bb[q] = lo;
+                        ll[q] = hi - lo;
+                    }
+                    b0 = bb[0]; l0 = ll[0];
+                    b1 = bb[1]; l1 = ll[1];
+                    b2 = bb[2]; l2 = ll[2];
+                }
                 const uint32_t tot = act ? l0 + l1 + l2 : 0u;
                 const uint32_t o1 = b1 - l0, o2 = b2 - l0 - l1;
                 uint32_t kmax = tot;
@@ -806,10 +891,10 @@ __device__ __forceinline__ int find_sim(const Batch& b, uint32_t blk, uint32_t* 
 
 #define MTPT_BATCH_PROLOGUE                                                                     \
     uint32_t l;                                                                                 \
-    const SimArgs& a = b.args[find_sim(b, blockIdx.x, &l)]
+    const SimArgs& a = b.args[find_sim(b, xcd_block(blockIdx.x, gridDim.x), &l)]
 
 template <int D, typename T>
-__global__ __launch_bounds__(kBlock) void bin_k(SimArgs a) { bin_body<D, T>(a, blockIdx.x); }
+__global__ __launch_bounds__(kBlock) void bin_k(SimArgs a) { bin_body<D, T>(a, xcd_block(blockIdx.x, gridDim.x)); }
 template <int D, typename T>
 __global__ __launch_bounds__(kBlock) void bin_kb(Batch b) { MTPT_BATCH_PROLOGUE; bin_body<D, T>(a, l); }
 
@@ -819,13 +904,13 @@ __global__ __launch_bounds__(kBlock) void scan_top_k(SimArgs a) { scan_top_body(
 __global__ __launch_bounds__(kBlock) void scan_top_kb(Batch b) { MTPT_BATCH_PROLOGUE; (void)l; scan_top_body(a.bsum, a.scan_blocks); }
 __global__ __launch_bounds__(kBlock) void scan_down_k(SimArgs a) { scan_down_body(a.counts, a.starts, a.bsum, blockIdx.x, true); }
 __global__ __launch_bounds__(kBlock) void scan_down_kb(Batch b) { MTPT_BATCH_PROLOGUE; scan_down_body(a.counts, a.starts, a.bsum, l, true); }
-__global__ __launch_bounds__(kBlock) void scatter_k(SimArgs a) { scatter_body(a, blockIdx.x); }
+__global__ __launch_bounds__(kBlock) void scatter_k(SimArgs a) { scatter_body(a, xcd_block(blockIdx.x, gridDim.x)); }
 __global__ __launch_bounds__(kBlock) void scatter_kb(Batch b) { MTPT_BATCH_PROLOGUE; scatter_body(a, l); }
 
 template <int D, int PREC>
 __global__ __launch_bounds__(kBlock) void place_k(SimArgs a)
 {
-    place_body<D, typename Types<PREC>::T, typename Types<PREC>::M>(a, blockIdx.x);
+    place_body<D, typename Types<PREC>::T, typename Types<PREC>::M>(a, xcd_block(blockIdx.x, gridDim.x));
 }
 template <int D, int PREC>
 __global__ __launch_bounds__(kBlock) void place_kb(Batch b)
@@ -835,12 +920,12 @@ __global__ __launch_bounds__(kBlock) void place_kb(Batch b)
 }
 
 template <int D, int PREC>
-__global__ __launch_bounds__(kBlock) void rowsum_k(SimArgs a) { tile_body<D, PREC, 1, false>(a, blockIdx.x); }
+__global__ __launch_bounds__(kBlock) void rowsum_k(SimArgs a) { tile_body<D, PREC, 1, false>(a, xcd_block(blockIdx.x, gridDim.x)); }
 template <int D, int PREC>
 __global__ __launch_bounds__(kBlock) void rowsum_kb(Batch b) { MTPT_BATCH_PROLOGUE; tile_body<D, PREC, 1, false>(a, l); }
 
 template <int D, int PREC, int NS>
-__global__ __launch_bounds__(kBlock) void transfer_k(SimArgs a) { tile_body<D, PREC, NS, true>(a, blockIdx.x); }
+__global__ __launch_bounds__(kBlock) void transfer_k(SimArgs a) { tile_body<D, PREC, NS, true>(a, xcd_block(blockIdx.x, gridDim.x)); }
 template <int D, int PREC, int NS>
 __global__ __launch_bounds__(kBlock) void transfer_kb(Batch b) { MTPT_BATCH_PROLOGUE; tile_body<D, PREC, NS, true>(a, l); }
 

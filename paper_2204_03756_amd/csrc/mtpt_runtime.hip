@@ -84,6 +84,7 @@ struct Plan {
     uint32_t scan_blocks = 1, part_blocks = 0;
     int tile[2] = {1, 1};
     uint32_t tiles_x = 1, tiles_y = 1, ntiles = 0;
+    bool trim_rows = false;
     size_t tsz = 8, msz = 8;
     size_t off_x[3]{}, off_xt[3]{}, off_m[2][3]{}, off_p[2]{}, off_s = 0, off_cell = 0, off_rank = 0,
            off_perm = 0, off_counts = 0, off_starts = 0, off_bsum = 0, off_part = 0, off_pair = 0,
@@ -164,13 +165,13 @@ Plan make_plan(const mtpt_params& p)
     }
     q.scan_blocks = static_cast<uint32_t>((static_cast<uint64_t>(q.ncells) + 1 + kScanTile - 1) / kScanTile);
     q.part_blocks = static_cast<uint32_t>((q.n + kBlock - 1) / kBlock);
-    // tiles of the mass-transfer passes: about one particle per thread, and
-    // the tile plus its one-cell halo expected to fill at most 1/1.6 of the
-    // LDS staging capacity (a fuller tile falls back to global reads)
+    // tiles of the mass-transfer passes: about 640 own particles, and the
+    // tile plus its one-cell halo expected to fill at most 1/1.25 of the LDS
+    // staging capacity (a fuller tile falls back to global reads)
     {
         const double rho_c = static_cast<double>(q.n) / static_cast<double>(q.ncells);
         const int planes = q.dim == 3 ? 3 : 1;
-        const double cap = static_cast<double>(tile_capacity(q.dim, q.prec, q.ns)) / 1.6;
+        const double cap = static_cast<double>(tile_capacity(q.dim, q.prec, q.ns)) / 1.25;
         const double cells_own = std::max(1.0, 640.0 / std::max(rho_c, 1e-9));
         int t = static_cast<int>(std::lround(std::sqrt(cells_own)));
         int tx = std::max(1, std::min(t, std::min(q.nc[0], tile_max(q.dim))));
@@ -186,6 +187,9 @@ Plan make_plan(const mtpt_params& p)
         q.tiles_x = static_cast<uint32_t>((q.nc[0] + tx - 1) / tx);
         q.tiles_y = static_cast<uint32_t>((q.nc[1] + ty - 1) / ty);
         q.ntiles = q.tiles_x * q.tiles_y * static_cast<uint32_t>(q.dim == 3 ? q.nc[2] : 1);
+        // rows of three cells long enough that trimming them to the x-window
+        // saves more candidates than its two binary searches cost
+        q.trim_rows = 3.0 * rho_c >= 12.0;
     }
     const size_t n = static_cast<size_t>(q.n);
     size_t off = 0;
@@ -307,11 +311,26 @@ SimArgs base_args(const mtpt_sim* s)
     a.tiles_x = q.tiles_x;
     a.tiles_y = q.tiles_y;
     a.ntiles = q.ntiles;
+    a.trim_rows = q.trim_rows ? 1 : 0;
     a.sdev = std::sqrt(2.0 * p.d_rw * p.dt);
     a.seed = p.seed;
     a.psi = q.psi;
     a.psi2 = q.psi * q.psi;
     a.win = q.psi * (1.0 + 1e-6);
+    a.win2d = a.win * a.win;
+    a.win2f = static_cast<float>(a.win2d);
+    {
+        // rounding margin of the per-row windows: 8 ulps of the largest
+        // coordinate plus 8 ulps of the window, in the type of the positions
+        double xmax = 0.0;
+        for (int k = 0; k < q.dim; ++k)
+            xmax = std::max(xmax, std::max(std::fabs(p.lo[k]), std::fabs(p.hi[k])));
+        const int e = xmax > 0.0 ? std::ilogb(xmax) : 0;
+        a.wmarginf = static_cast<float>(8.0 * std::ldexp(1.0, e - 23) + 8.0 * 1.1920928955078125e-7 * a.win);
+        a.wmargind = 8.0 * std::ldexp(1.0, e - 52) + 8.0 * 2.220446049250313e-16 * a.win;
+    }
+    for (int k = 0; k < 3; ++k)
+        a.side[k] = q.inv_side[k] > 0.0 ? 1.0 / q.inv_side[k] : 0.0;
     a.psi2_in = static_cast<float>(a.psi2 * (1.0 - 1e-5));
     a.psi2_out = static_cast<float>(a.psi2 * (1.0 + 1e-5));
     a.kc = p.beta / (4.0 * p.d_mt * p.dt);
