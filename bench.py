@@ -22,7 +22,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12   # lane-ops/s: 256 CUs x 64 lanes x 2.4 GHz
+VALU_PEAK_GOPS = 256 * 64 * 2.4e9 / 1e9    # VALU lane-slots/s: 256 CUs x 64 lanes x 2.4 GHz
 
 
 def algorithmic_bytes(kernel: str, n: int, dim: int, ns: int, tsz: int, msz: int, ncells: int) -> float:
@@ -89,31 +89,78 @@ def run_path(mt, W, precision: int, steps: int, warmup: int, profile_steps: int 
     }
 
 
-def roofline(res, dim, ns, tsz, msz, n):
+# Algorithmic VALU lane-slots (one slot = one lane of one full-rate VALU
+# instruction; transcendentals count 4, FP64 arithmetic 2), per ordered pair
+# within psi and per particle, of the two ALU-bound passes:
+#   rowsum   r^2 (2d), cutoff test, scale, exp (4), add            = 2d + 7
+#   transfer the same K (2d + 6), W = 2K rcp(s_i + s_j) (7), and per
+#            species the increment (FP32W: FP64 sub, cvt, FP64 fma = 5;
+#            Kahan: 8 FP32 ops; FP64: 6)                           = 2d + 13 + c S
+#   walk     (fused into transfer) per particle and Philox call: Philox4x32-10
+#            (~100 integer ops) + Box-Muller in FP64 (~125 ops = 250 slots)
+#            + reflect/cell (~30): 380, two calls in 3-d
+# The FP64 path's pair terms are doubled (FP64 at half rate) plus 40 for the
+# FP64 exp and 40 for the FP64 divide.
+def algorithmic_slots(kernel: str, n: int, pairs: int, dim: int, ns: int, prec: str) -> float:
+    walk = 380.0 * (2 if dim == 3 else 1)
+    per_species = {"fp32w": 5.0, "kahan": 8.0, "fp64": 6.0}[prec]
+    if kernel == "rowsum":
+        per = 2 * dim + 7.0
+        if prec == "fp64":
+            per = 2 * per + 40.0
+        return pairs * per
+    if kernel == "transfer":
+        per = 2 * dim + 13.0
+        if prec == "fp64":
+            per = 2 * per + 80.0
+        return pairs * (per + per_species * ns) + n * walk
+    return 0.0
+
+
+def roofline(res, dim, ns, tsz, msz, n, prec="fp32w"):
     phases = res["phases"]
     if not phases:
         return None
     name = max(phases, key=lambda k: phases[k][0])
     ms_total, launches = phases[name]
     avg_s = ms_total / launches / 1e3
+    common = {"kernel": name, "avg_launch_us": round(avg_s * 1e6, 2),
+              "phase_ms_per_step": {k: round(v[0] / v[1], 4) for k, v in phases.items()}}
+    if name in ("rowsum", "transfer"):
+        slots = algorithmic_slots(name, n, res["pairs_per_step"], dim, ns, prec)
+        achieved = slots / avg_s / 1e9
+        return {**common, "bound": "alu", "achieved": round(achieved, 1), "peak": VALU_PEAK_GOPS,
+                "unit": "Gop/s", "frac": round(achieved / VALU_PEAK_GOPS, 4), "traffic": None,
+                "ops_per_launch": slots,
+                "hbm_algorithmic_GBps": round(algorithmic_bytes(name, n, dim, ns, tsz, msz,
+                                                                res["n_cells"]) / avg_s / 1e9, 1)}
     byt = algorithmic_bytes(name, n, dim, ns, tsz, msz, res["n_cells"])
     achieved = byt / avg_s / 1e9
-    return {"kernel": name, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+    return {**common, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-            "avg_launch_us": round(avg_s * 1e6, 2), "bytes_per_launch": byt,
-            "phase_ms_per_step": {k: round(v[0] / v[1], 4) for k, v in phases.items()}}
+            "bytes_per_launch": byt}
+
+
+def source_sha256() -> str:
+    """sha256 over the library's sources (kernels, headers, runtime), in name order."""
+    import hashlib
+    d = os.path.join(ROOT, "paper_2204_03756_amd", "csrc")
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(d)):
+        if f.endswith((".hip", ".h")):
+            h.update(f.encode())
+            h.update(open(os.path.join(d, f), "rb").read())
+    return h.hexdigest()
 
 
 def traffic_from_profile(kernel: str, workload: str, precision: str):
     """HBM bytes per launch of a kernel from the committed PMC summary, or
     None when the kernel source changed since the counters were taken."""
-    import hashlib
-    src = os.path.join(ROOT, "paper_2204_03756_amd", "csrc", "mtpt_kernels.hip")
     path = os.path.join(ROOT, "profiles", f"traffic_{workload}_{precision}.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
-    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    sha = source_sha256()
     k = rec.get("kernels", {}).get(kernel)
     if rec.get("source_sha256") != sha or k is None:
         return None
@@ -249,7 +296,7 @@ def main():
         "mass_drift": r32["drift"],
     }
     ns = p.n_species
-    out["roofline"] = roofline(r32, p.dim, ns, 4, 8, p.n)
+    out["roofline"] = roofline(r32, p.dim, ns, 4, 8, p.n, "fp32w")
     if out["roofline"]:
         t = traffic_from_profile(out["roofline"]["kernel"], workload, "fp32w")
         out["roofline"]["traffic"] = t
@@ -257,13 +304,13 @@ def main():
         rk = run_path(mt, W, W.FP32_KAHAN, args.steps, args.warmup, workload=workload)
         out["kahan_path"] = {"value": rk["value"], "ms_per_step": rk["ms_per_step"],
                              "p50_step_ms": rk["p50_ms"], "p99_step_ms": rk["p99_ms"],
-                             "mass_drift": rk["drift"], "roofline": roofline(rk, p.dim, ns, 4, 4, p.n)}
+                             "mass_drift": rk["drift"], "roofline": roofline(rk, p.dim, ns, 4, 4, p.n, "kahan")}
     if not args.no_fp64:
         r64 = run_path(mt, W, W.FP64, args.steps, args.warmup, workload=workload)
         out["fp64_path"] = {"value": r64["value"], "ms_per_step": r64["ms_per_step"],
                             "p50_step_ms": r64["p50_ms"], "p99_step_ms": r64["p99_ms"],
                             "mass_drift": r64["drift"],
-                            "roofline": roofline(r64, p.dim, ns, 8, 8, p.n)}
+                            "roofline": roofline(r64, p.dim, ns, 8, 8, p.n, "fp64")}
         out["fp32_over_fp64"] = r32["value"] / r64["value"]
     if not args.no_cpu and workload == "rw2d":
         out["cpu_baseline"] = cpu_baseline(W)
