@@ -21,15 +21,17 @@ FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",
          "-Wall", "-Wno-unused-result", "-I", os.path.join(ROOT, "include")]
 
 
-def build(verbose: bool = False) -> str:
-    """Compile libmtpt.so next to this file; returns its path."""
-    tmp = LIB + ".tmp"
-    cmd = [HIPCC, *FLAGS, *SOURCES, "-o", tmp]
+def build(verbose: bool = False, out: str = None, defines=()) -> str:
+    """Compile libmtpt.so (next to this file unless ``out`` is given; extra
+    ``-D`` tuning defines in ``defines``); returns its path."""
+    lib = out or LIB
+    tmp = lib + ".tmp"
+    cmd = [HIPCC, *FLAGS, *[f"-D{d}" for d in defines], *SOURCES, "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, lib)
+    return lib
 
 
 def stale() -> bool:

@@ -29,7 +29,15 @@ constexpr int kScanTile = kBlock * kScanItems;
 constexpr int kFinalBlock = 1024;    // threads of the finalize kernel
 // bytes of staged particle data per workgroup of the mass-transfer passes
 // (3-d halos hold three planes of cell rows)
-template <int D> struct LdsBudget { static constexpr int value = D == 2 ? 24576 : 46080; };
+#ifndef MTPT_LDS_BUDGET_2D
+#define MTPT_LDS_BUDGET_2D 16384
+#endif
+#ifndef MTPT_LDS_BUDGET_3D
+#define MTPT_LDS_BUDGET_3D 46080
+#endif
+template <int D> struct LdsBudget {
+    static constexpr int value = D == 2 ? MTPT_LDS_BUDGET_2D : MTPT_LDS_BUDGET_3D;
+};
 
 // Largest tile (cells in x and in y) of the mass-transfer passes, the halo
 // cell rows it spans and the cell boundaries kept per halo row.

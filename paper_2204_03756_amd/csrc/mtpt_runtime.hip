@@ -172,7 +172,10 @@ Plan make_plan(const mtpt_params& p)
         const double rho_c = static_cast<double>(q.n) / static_cast<double>(q.ncells);
         const int planes = q.dim == 3 ? 3 : 1;
         const double cap = static_cast<double>(tile_capacity(q.dim, q.prec, q.ns)) / 1.25;
-        const double cells_own = std::max(1.0, 640.0 / std::max(rho_c, 1e-9));
+#ifndef MTPT_TILE_OWN
+#define MTPT_TILE_OWN 640.0
+#endif
+        const double cells_own = std::max(1.0, MTPT_TILE_OWN / std::max(rho_c, 1e-9));
         int t = static_cast<int>(std::lround(std::sqrt(cells_own)));
         int tx = std::max(1, std::min(t, std::min(q.nc[0], tile_max(q.dim))));
         int ty = std::max(1, std::min(t, std::min(q.nc[1], tile_max(q.dim))));

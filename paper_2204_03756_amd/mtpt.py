@@ -62,7 +62,8 @@ _i64p = C.POINTER(C.c_int64)
 
 
 def lib_path() -> str:
-    return _build.LIB
+    """libmtpt.so next to this package, or the file named by MTPT_LIB."""
+    return os.environ.get("MTPT_LIB") or _build.LIB
 
 
 def load():
@@ -70,7 +71,7 @@ def load():
     global _LIB
     if _LIB is not None:
         return _LIB
-    path = _build.LIB
+    path = lib_path()
     if not os.path.exists(path):
         raise ImportError(f"libmtpt.so not found at {path}: run __graft_entry__.build() "
                           "(or python paper_2204_03756_amd/build.py) first")
