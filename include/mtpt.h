@@ -66,7 +66,7 @@ enum { MTPT_FP64 = 0, MTPT_FP32W_FP64ACC = 1, MTPT_FP32_KAHAN = 2 };
 typedef struct {
     uint32_t abi_version; /* must be MTPT_ABI_VERSION */
     int32_t dim;          /* 2 or 3 */
-    int64_t n;            /* particles, >= 0 */
+    int64_t n;            /* particles, 0 <= n <= 2^31 - 256 */
     int32_t n_species;    /* 1, or 3 (A, B, C with the A+B->C reaction) */
     int32_t precision;    /* MTPT_FP64 / MTPT_FP32W_FP64ACC / MTPT_FP32_KAHAN */
     double lo[3], hi[3];  /* box [lo, hi]^dim, reflecting walls, hi > lo */

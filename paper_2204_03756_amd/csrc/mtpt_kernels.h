@@ -42,8 +42,8 @@ template <int D> struct LdsBudget {
 // Largest tile (cells in x and in y) of the mass-transfer passes, the halo
 // cell rows it spans and the cell boundaries kept per halo row.
 template <int D> struct TileLimits {
-    static constexpr int max_x = D == 2 ? 32 : 16;
-    static constexpr int max_y = D == 2 ? 32 : 16;
+    static constexpr int max_x = D == 2 ? 24 : 16;
+    static constexpr int max_y = D == 2 ? 24 : 16;
     static constexpr int segs = (D == 3 ? 3 : 1) * (max_y + 2);
     static constexpr int cols = max_x + 3;
 };
@@ -109,7 +109,8 @@ struct SimArgs {
     uint32_t* cell;
     uint32_t* rank;
     uint32_t* perm;
-    uint32_t* counts;
+    uint32_t* counts;        // per-cell histogram filled with global atomics
+    uint32_t* tcounts;       // per-cell counts of particles that stayed in their tile
     uint32_t* starts;
     uint32_t* bsum;
     double* partials;
@@ -120,6 +121,8 @@ struct SimArgs {
     int32_t recompute_s;     // the row-sum pass ran this step
     int32_t walk;            // apply the jump in the bin pass (0 at create)
     int32_t fuse_bin;        // the transfer pass also bins for the next step
+    int32_t tcounts_valid;   // this step's binning came from the transfer pass:
+                             // cell count = counts + tcounts
     int32_t trim_rows;       // trim candidate rows to the per-row x-window
 };
 

@@ -293,15 +293,25 @@ __device__ __forceinline__ void bin_body(const SimArgs& a, uint32_t blk)
     a.rank[i] = atomicAdd(&a.counts[c], 1u);
 }
 
-__device__ __forceinline__ void scan_reduce_body(const uint32_t* in, uint32_t* bsum, uint32_t blk)
+// Counts to scan are in[c] (+ in2[c] when in2 is given).
+__device__ __forceinline__ void scan_reduce_body(const uint32_t* in, const uint32_t* in2, uint32_t* bsum,
+                                                 uint32_t blk)
 {
-    const uint4* p = reinterpret_cast<const uint4*>(in + static_cast<size_t>(blk) * kScanTile +
-                                                    threadIdx.x * kScanItems);
+    const size_t base = static_cast<size_t>(blk) * kScanTile + threadIdx.x * kScanItems;
+    const uint4* p = reinterpret_cast<const uint4*>(in + base);
     uint32_t s = 0;
 #pragma unroll
     for (int q = 0; q < kScanItems / 4; ++q) {
         const uint4 w = p[q];
         s += w.x + w.y + w.z + w.w;
+    }
+    if (in2) {
+        const uint4* p2 = reinterpret_cast<const uint4*>(in2 + base);
+#pragma unroll
+        for (int q = 0; q < kScanItems / 4; ++q) {
+            const uint4 w = p2[q];
+            s += w.x + w.y + w.z + w.w;
+        }
     }
     const uint32_t t = block_sum<kBlock, uint32_t>(s);
     if (threadIdx.x == 0)
@@ -322,8 +332,8 @@ __device__ __forceinline__ void scan_top_body(uint32_t* bsum, uint32_t nb)
     }
 }
 
-__device__ __forceinline__ void scan_down_body(uint32_t* in, uint32_t* out, const uint32_t* bsum,
-                                               uint32_t blk, bool zero_in)
+__device__ __forceinline__ void scan_down_body(uint32_t* in, const uint32_t* in2, uint32_t* out,
+                                               const uint32_t* bsum, uint32_t blk, bool zero_in)
 {
     const size_t base = static_cast<size_t>(blk) * kScanTile + threadIdx.x * kScanItems;
     uint4* p = reinterpret_cast<uint4*>(in + base);
@@ -332,6 +342,14 @@ __device__ __forceinline__ void scan_down_body(uint32_t* in, uint32_t* out, cons
     for (int q = 0; q < kScanItems / 4; ++q) {
         const uint4 w = p[q];
         v[4 * q + 0] = w.x; v[4 * q + 1] = w.y; v[4 * q + 2] = w.z; v[4 * q + 3] = w.w;
+    }
+    if (in2) {
+        const uint4* p2 = reinterpret_cast<const uint4*>(in2 + base);
+#pragma unroll
+        for (int q = 0; q < kScanItems / 4; ++q) {
+            const uint4 w = p2[q];
+            v[4 * q + 0] += w.x; v[4 * q + 1] += w.y; v[4 * q + 2] += w.z; v[4 * q + 3] += w.w;
+        }
     }
     uint32_t s = 0;
 #pragma unroll
@@ -358,7 +376,18 @@ __device__ __forceinline__ void scatter_body(const SimArgs& a, uint32_t blk)
     const int64_t i = static_cast<int64_t>(blk) * kBlock + threadIdx.x;
     if (i >= a.n)
         return;
-    a.perm[a.starts[a.cell[i]] + a.rank[i]] = static_cast<uint32_t>(i);
+    const uint32_t c = a.cell[i];
+    const uint32_t r = a.rank[i];
+    uint32_t slot = a.starts[c];
+    if (a.tcounts_valid) {
+        // slots of a cell: its tile's own particles first, then the arrivals
+        // from other tiles (rank flagged in bit 31)
+        slot += (r >> 31) ? a.tcounts[c] : 0u;
+        slot += r & 0x7fffffffu;
+    } else {
+        slot += r;
+    }
+    a.perm[slot] = static_cast<uint32_t>(i);
 }
 
 // Slot k holds particle src after the scatter, in arbitrary order inside its
@@ -497,24 +526,31 @@ __device__ __forceinline__ void scan_row(const SimArgs& a, PX p, PS sr, PM ms, u
 
 // Walk, cell id and histogram slot of sorted particle i for the step after
 // a.step (the next step's binning, done while its position is in registers).
+// A particle that stays inside the tile (cells [tlo, thi) per axis) takes
+// its slot from the tile's LDS histogram hist; one that leaves takes it from
+// the global histogram, flagged in bit 31 of its rank.
 template <int D, typename T>
-__device__ __forceinline__ void bin_next(const SimArgs& a, uint32_t i, const T* x)
+__device__ __forceinline__ void bin_next(const SimArgs& a, uint32_t i, const T* x, const int* tlo,
+                                         const int* thi, uint32_t* hist)
 {
     const uint32_t pid = a.pid_dst[i];
     double z[3], spare;
     normal_pair(a.seed, a.step + 1, pid, 0u, &z[0], &z[1]);
     if (D == 3)
         normal_pair(a.seed, a.step + 1, pid, 1u, &z[2], &spare);
-    uint32_t c = 0;
+    uint32_t c = 0, lc = 0;
+    bool inside = true;
 #pragma unroll
     for (int k = D - 1; k >= 0; --k) {
         const T v = walk_reflect<T>(x[k], z[k], a.sdev, a.lo[k], a.hi[k], a.lof[k], a.hif[k]);
         static_cast<T*>(a.xt[k])[i] = v;
-        c = c * static_cast<uint32_t>(a.nc[k]) +
-            static_cast<uint32_t>(cell_coord(static_cast<double>(v), a.glo[k], a.inv_side[k], a.nc[k]));
+        const int ck = cell_coord(static_cast<double>(v), a.glo[k], a.inv_side[k], a.nc[k]);
+        c = c * static_cast<uint32_t>(a.nc[k]) + static_cast<uint32_t>(ck);
+        inside = inside && ck >= tlo[k] && ck < thi[k];
+        lc = lc * static_cast<uint32_t>(thi[k] - tlo[k]) + static_cast<uint32_t>(ck - tlo[k]);
     }
     a.cell[i] = c;
-    a.rank[i] = atomicAdd(&a.counts[c], 1u);
+    a.rank[i] = inside ? atomicAdd(&hist[lc], 1u) : (0x80000000u | atomicAdd(&a.counts[c], 1u));
 }
 
 // One tile: tx * ty cells of plane tz.  Halo rows (cells xa..xb-1 of rows
@@ -539,6 +575,8 @@ __device__ __forceinline__ void tile_body(const SimArgs& a, uint32_t blk)
     __shared__ uint32_t cst[kSegs][TileLimits<D>::cols];
     __shared__ uint32_t own_gb[kRows];
     __shared__ uint32_t own_pre[kRows + 1];
+    constexpr int kHist = TRANSFER ? TileLimits<D>::max_x * TileLimits<D>::max_y : 1;
+    __shared__ uint32_t hist[kHist];
 
     const int tid = threadIdx.x;
     const int nc0 = a.nc[0], nc1 = a.nc[1], nc2 = a.nc[2];
@@ -557,6 +595,10 @@ __device__ __forceinline__ void tile_body(const SimArgs& a, uint32_t blk)
     const int xa = x0 > 0 ? x0 - 1 : 0;
     const int xb = x1 < nc0 ? x1 + 1 : nc0;
     const int ncol = xb - xa;
+    const int tw = x1 - x0;
+    if (TRANSFER && a.fuse_bin)
+        for (int k = tid; k < tw * nrow; k += kBlock)
+            hist[k] = 0u;
 
     uint32_t slen = 0;
     if (tid < nseg) {
@@ -824,8 +866,20 @@ __device__ __forceinline__ void tile_body(const SimArgs& a, uint32_t blk)
                 static_cast<M*>(a.m_dst[c])[i] = st;
                 msum[c] += static_cast<double>(st);
             }
-            if (a.fuse_bin)
-                bin_next<D, T>(a, i, xi);
+            if (a.fuse_bin) {
+                const int tlo[3] = {x0, y0, tz};
+                const int thi[3] = {x1, y1, tz + 1};
+                bin_next<D, T>(a, i, xi, tlo, thi, hist);
+            }
+        }
+    }
+    if (TRANSFER && a.fuse_bin) {
+        // counts of the tile's cells from the particles that stayed in it
+        __syncthreads();
+        for (int k = tid; k < tw * nrow; k += kBlock) {
+            const int ry = k / tw;
+            const uint32_t c = (static_cast<uint32_t>(D == 3 ? tz : 0) * nc1 + (y0 + ry)) * nc0 + x0 + (k - ry * tw);
+            a.tcounts[c] = hist[k];
         }
     }
     if constexpr (!TRANSFER) {
@@ -898,12 +952,12 @@ __global__ __launch_bounds__(kBlock) void bin_k(SimArgs a) { bin_body<D, T>(a, x
 template <int D, typename T>
 __global__ __launch_bounds__(kBlock) void bin_kb(Batch b) { MTPT_BATCH_PROLOGUE; bin_body<D, T>(a, l); }
 
-__global__ __launch_bounds__(kBlock) void scan_reduce_k(SimArgs a) { scan_reduce_body(a.counts, a.bsum, blockIdx.x); }
-__global__ __launch_bounds__(kBlock) void scan_reduce_kb(Batch b) { MTPT_BATCH_PROLOGUE; scan_reduce_body(a.counts, a.bsum, l); }
+__global__ __launch_bounds__(kBlock) void scan_reduce_k(SimArgs a) { scan_reduce_body(a.counts, a.tcounts_valid ? a.tcounts : nullptr, a.bsum, blockIdx.x); }
+__global__ __launch_bounds__(kBlock) void scan_reduce_kb(Batch b) { MTPT_BATCH_PROLOGUE; scan_reduce_body(a.counts, a.tcounts_valid ? a.tcounts : nullptr, a.bsum, l); }
 __global__ __launch_bounds__(kBlock) void scan_top_k(SimArgs a) { scan_top_body(a.bsum, a.scan_blocks); }
 __global__ __launch_bounds__(kBlock) void scan_top_kb(Batch b) { MTPT_BATCH_PROLOGUE; (void)l; scan_top_body(a.bsum, a.scan_blocks); }
-__global__ __launch_bounds__(kBlock) void scan_down_k(SimArgs a) { scan_down_body(a.counts, a.starts, a.bsum, blockIdx.x, true); }
-__global__ __launch_bounds__(kBlock) void scan_down_kb(Batch b) { MTPT_BATCH_PROLOGUE; scan_down_body(a.counts, a.starts, a.bsum, l, true); }
+__global__ __launch_bounds__(kBlock) void scan_down_k(SimArgs a) { scan_down_body(a.counts, a.tcounts_valid ? a.tcounts : nullptr, a.starts, a.bsum, blockIdx.x, true); }
+__global__ __launch_bounds__(kBlock) void scan_down_kb(Batch b) { MTPT_BATCH_PROLOGUE; scan_down_body(a.counts, a.tcounts_valid ? a.tcounts : nullptr, a.starts, a.bsum, l, true); }
 __global__ __launch_bounds__(kBlock) void scatter_k(SimArgs a) { scatter_body(a, xcd_block(blockIdx.x, gridDim.x)); }
 __global__ __launch_bounds__(kBlock) void scatter_kb(Batch b) { MTPT_BATCH_PROLOGUE; scatter_body(a, l); }
 
@@ -1084,11 +1138,11 @@ __global__ __launch_bounds__(kBlock) void copy_pad_k(const uint32_t* in, uint32_
     if (k < padded)
         out[k] = k < len ? in[k] : 0u;
 }
-__global__ __launch_bounds__(kBlock) void scan_reduce_raw_k(const uint32_t* in, uint32_t* bsum) { scan_reduce_body(in, bsum, blockIdx.x); }
+__global__ __launch_bounds__(kBlock) void scan_reduce_raw_k(const uint32_t* in, uint32_t* bsum) { scan_reduce_body(in, nullptr, bsum, blockIdx.x); }
 __global__ __launch_bounds__(kBlock) void scan_top_raw_k(uint32_t* bsum, uint32_t nb) { scan_top_body(bsum, nb); }
 __global__ __launch_bounds__(kBlock) void scan_down_raw_k(uint32_t* in, uint32_t* out, const uint32_t* bsum)
 {
-    scan_down_body(in, out, bsum, blockIdx.x, false);
+    scan_down_body(in, nullptr, out, bsum, blockIdx.x, false);
 }
 
 // ------------------------------------------------------------- host side

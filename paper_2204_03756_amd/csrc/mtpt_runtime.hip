@@ -87,7 +87,7 @@ struct Plan {
     bool trim_rows = false;
     size_t tsz = 8, msz = 8;
     size_t off_x[3]{}, off_xt[3]{}, off_m[2][3]{}, off_p[2]{}, off_s = 0, off_cell = 0, off_rank = 0,
-           off_perm = 0, off_counts = 0, off_starts = 0, off_bsum = 0, off_part = 0, off_pair = 0,
+           off_perm = 0, off_counts = 0, off_tcounts = 0, off_starts = 0, off_bsum = 0, off_part = 0, off_pair = 0,
            off_stats = 0;
     size_t bytes = 0;
 };
@@ -100,8 +100,8 @@ int validate(const mtpt_params* p)
         return fail(MTPT_E_ABI, "abi_version %u, library has %d", p->abi_version, MTPT_ABI_VERSION);
     if (p->dim != 2 && p->dim != 3)
         return fail(MTPT_E_ARG, "dim must be 2 or 3 (got %d)", p->dim);
-    if (p->n < 0 || p->n > 0xFFFFFF00ll)
-        return fail(MTPT_E_ARG, "n must be in [0, 2^32 - 256] (got %lld)", (long long)p->n);
+    if (p->n < 0 || p->n > 0x7FFFFF00ll)
+        return fail(MTPT_E_ARG, "n must be in [0, 2^31 - 256] (got %lld)", (long long)p->n);
     if (p->n_species != 1 && p->n_species != 3)
         return fail(MTPT_E_ARG, "n_species must be 1 or 3 (got %d)", p->n_species);
     if (p->precision < 0 || p->precision > 2)
@@ -216,6 +216,7 @@ Plan make_plan(const mtpt_params& p)
     q.off_perm = take(n * 4);
     const size_t padded = static_cast<size_t>(q.scan_blocks) * kScanTile;
     q.off_counts = take(padded * 4);
+    q.off_tcounts = take(padded * 4);
     q.off_starts = take(padded * 4);
     q.off_bsum = take(static_cast<size_t>(q.scan_blocks) * 4);
     q.off_part = take(static_cast<size_t>(std::max<uint32_t>(std::max(q.part_blocks, q.ntiles), 1)) * 3 * 8);
@@ -244,8 +245,8 @@ struct mtpt_sim {
     void* M[2][3]{};
     uint32_t* P[2]{};
     void* S = nullptr;
-    uint32_t *cell = nullptr, *rank = nullptr, *perm = nullptr, *counts = nullptr, *starts = nullptr,
-             *bsum = nullptr;
+    uint32_t *cell = nullptr, *rank = nullptr, *perm = nullptr, *counts = nullptr, *tcounts = nullptr,
+             *starts = nullptr, *bsum = nullptr;
     double* partials = nullptr;
     uint32_t* pair_part = nullptr;
     DevStats* st = nullptr;
@@ -283,6 +284,7 @@ void carve(mtpt_sim* s)
     s->rank = reinterpret_cast<uint32_t*>(b + q.off_rank);
     s->perm = reinterpret_cast<uint32_t*>(b + q.off_perm);
     s->counts = reinterpret_cast<uint32_t*>(b + q.off_counts);
+    s->tcounts = reinterpret_cast<uint32_t*>(b + q.off_tcounts);
     s->starts = reinterpret_cast<uint32_t*>(b + q.off_starts);
     s->bsum = reinterpret_cast<uint32_t*>(b + q.off_bsum);
     s->partials = reinterpret_cast<double*>(b + q.off_part);
@@ -357,6 +359,7 @@ SimArgs base_args(const mtpt_sim* s)
     a.rank = s->rank;
     a.perm = s->perm;
     a.counts = s->counts;
+    a.tcounts = s->tcounts;
     a.starts = s->starts;
     a.bsum = s->bsum;
     a.partials = s->partials;
@@ -401,6 +404,7 @@ SimArgs step_args(const mtpt_sim* s, bool* rowsum_needed)
         a.recompute_s = s->s_valid ? 0 : 1;
     }
     a.fuse_bin = s->moving ? 1 : 0;
+    a.tcounts_valid = (s->moving && s->bin_ready) ? 1 : 0;
     *rowsum_needed = a.recompute_s != 0;
     return a;
 }
@@ -509,6 +513,7 @@ int create_into(mtpt_sim* s, const double* pos, const double* mass)
     const size_t n = static_cast<size_t>(q.n);
     HIP_TRY(hipMemsetAsync(s->st, 0, sizeof(DevStats), s->stream));
     HIP_TRY(hipMemsetAsync(s->counts, 0, static_cast<size_t>(q.scan_blocks) * kScanTile * 4, s->stream));
+    HIP_TRY(hipMemsetAsync(s->tcounts, 0, static_cast<size_t>(q.scan_blocks) * kScanTile * 4, s->stream));
     if (n > 0) {
         std::vector<unsigned char> stage(std::max(n * q.tsz, n * q.msz));
         for (int k = 0; k < q.dim; ++k) {
