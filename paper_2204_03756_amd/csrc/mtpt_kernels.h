@@ -32,12 +32,23 @@ constexpr int kFinalBlock = 1024;    // threads of the finalize kernel
 #ifndef MTPT_LDS_BUDGET_2D
 #define MTPT_LDS_BUDGET_2D 16384
 #endif
+#ifndef MTPT_LDS_BUDGET_2D_F64
+#define MTPT_LDS_BUDGET_2D_F64 24576
+#endif
 #ifndef MTPT_LDS_BUDGET_3D
 #define MTPT_LDS_BUDGET_3D 46080
 #endif
-template <int D> struct LdsBudget {
-    static constexpr int value = D == 2 ? MTPT_LDS_BUDGET_2D : MTPT_LDS_BUDGET_3D;
+template <int D, int PREC> struct LdsBudget {
+    static constexpr int value = D == 3 ? MTPT_LDS_BUDGET_3D
+                                        : (PREC == 0 ? MTPT_LDS_BUDGET_2D_F64 : MTPT_LDS_BUDGET_2D);
 };
+// unroll factor of the candidate loop of the tiled passes
+#ifndef MTPT_CAND_UNROLL_2D
+#define MTPT_CAND_UNROLL_2D 1
+#endif
+#ifndef MTPT_CAND_UNROLL_3D
+#define MTPT_CAND_UNROLL_3D 4
+#endif
 
 // Largest tile (cells in x and in y) of the mass-transfer passes, the halo
 // cell rows it spans and the cell boundaries kept per halo row.
@@ -111,6 +122,7 @@ struct SimArgs {
     uint32_t* perm;
     uint32_t* counts;        // per-cell histogram filled with global atomics
     uint32_t* tcounts;       // per-cell counts of particles that stayed in their tile
+    uint64_t* cmask;         // [plane][n] neighbour bits of the candidate rows (row-sum pass)
     uint32_t* starts;
     uint32_t* bsum;
     double* partials;

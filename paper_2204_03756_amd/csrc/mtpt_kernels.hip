@@ -40,7 +40,7 @@ template <int D, int PREC, int NS, bool TRANSFER> struct TileCap {
     using M = typename Types<PREC>::M;
     static constexpr int bytes =
         D * static_cast<int>(sizeof(T)) + (TRANSFER ? static_cast<int>(sizeof(T) + NS * sizeof(M)) : 0);
-    static constexpr int value = LdsBudget<D>::value / bytes;
+    static constexpr int value = LdsBudget<D, PREC>::value / bytes;
 };
 
 __device__ __forceinline__ int cell_coord(double x, double glo, double inv, int nc)
@@ -72,6 +72,10 @@ __device__ __forceinline__ double r2_canonical(const double* xi, const double* x
 template <int D, typename T> struct Pair;
 
 template <int D> struct Pair<D, double> {
+    __device__ __forceinline__ static double r2(const double* xi, const double* xj)
+    {
+        return r2_canonical<D>(xi, xj);
+    }
     __device__ __forceinline__ static bool inside(const SimArgs& a, const double* xi,
                                                   const double* xj, double* r2o)
     {
@@ -87,19 +91,25 @@ template <int D> struct Pair<D, double> {
 };
 
 template <int D> struct Pair<D, float> {
-    __device__ __forceinline__ static bool inside(const SimArgs& a, const float* xi,
-                                                  const float* xj, float* r2o)
+    // FP32 r^2 with a fixed contraction: fma(d0, d0, d1 d1) (+ fma(d2, d2, .))
+    __device__ __forceinline__ static float r2(const float* xi, const float* xj)
     {
         const float d0 = xj[0] - xi[0];
         const float d1 = xj[1] - xi[1];
-        float r2 = d0 * d0 + d1 * d1;
+        float r = __builtin_fmaf(d0, d0, d1 * d1);
         if (D == 3) {
             const float d2 = xj[2] - xi[2];
-            r2 = r2 + d2 * d2;
+            r = __builtin_fmaf(d2, d2, r);
         }
+        return r;
+    }
+    __device__ __forceinline__ static bool inside(const SimArgs& a, const float* xi,
+                                                  const float* xj, float* r2o)
+    {
+        const float r2 = Pair::r2(xi, xj);
         *r2o = r2;
         bool in = r2 < a.psi2_in;
-        const bool band = (r2 >= a.psi2_in) & (r2 <= a.psi2_out);
+        const bool band = (r2 <= a.psi2_out) && !in;
         if (__builtin_expect(band, 0)) {
             double pi[3], pj[3];
 #pragma unroll
@@ -714,6 +724,8 @@ __device__ __forceinline__ void tile_body(const SimArgs& a, uint32_t blk)
             // LDS slot of particle i itself (the self pair is skipped by slot)
             const int smid = (planes == 3 ? rows : 0) + r + 1;
             const uint32_t li = i - seg_gb[smid] + seg_off[smid];
+            if constexpr (!TRANSFER)
+                acc.cnt = 1;   // self; the neighbours are counted from the masks
             // distances from the particle to the y (and z) slabs of the rows
             // below and above its own, less a rounding margin
             const int cyc = cell_coord(static_cast<double>(xi[1]), a.glo[1], a.inv_side[1], nc1);
@@ -788,22 +800,12 @@ __device__ __forceinline__ void tile_body(const SimArgs& a, uint32_t blk)
                 for (int off = 32; off >= 1; off >>= 1)
                     kmax = max(kmax, static_cast<uint32_t>(__shfl_xor(static_cast<int>(kmax), off, 64)));
                 kmax = __builtin_amdgcn_readfirstlane(kmax);
-                for (uint32_t k = 0; k < kmax; ++k) {
-                    const bool valid = k < tot;
-                    uint32_t idx = k + (k < l0 ? b0 : (k < l0 + l1 ? o1 : o2));
-                    idx = valid ? idx : li;
-                    T xj[3];
-#pragma unroll
-                    for (int d = 0; d < D; ++d)
-                        xj[d] = lpos[d][idx];
-                    T r2;
-                    bool in = Pair<D, T>::inside(a, xi, xj, &r2) && valid;
-                    if (TRANSFER)
-                        in = in && idx != li;
+                constexpr int kUnroll = D == 3 ? MTPT_CAND_UNROLL_3D : MTPT_CAND_UNROLL_2D;
+                // one candidate: LDS slot idx, pair counted when in
+                auto visit = [&](uint32_t idx, bool in, T r2) {
                     const T kv = Pair<D, T>::kernel(a, r2);
                     if constexpr (!TRANSFER) {
                         acc.s += in ? kv : T(0);
-                        acc.cnt += in ? 1u : 0u;
                     } else {
                         using A = typename Types<PREC>::A;
                         const T w = Pair<D, T>::weight(kv, acc.si, lsr[idx]);
@@ -822,7 +824,69 @@ __device__ __forceinline__ void tile_body(const SimArgs& a, uint32_t blk)
                             }
                         }
                     }
+                };
+                uint64_t* const pmask = a.cmask + static_cast<size_t>(pzr) * static_cast<size_t>(a.n);
+                if (TRANSFER && kmax <= 64u) {
+                    // neighbours recorded by the row-sum pass: bit k of the
+                    // mask is candidate k (same rows, same order) within psi
+                    uint64_t mk = act ? pmask[i] : 0ull;
+                    uint32_t cmax = static_cast<uint32_t>(__builtin_popcountll(mk));
+#pragma unroll
+                    for (int off = 32; off >= 1; off >>= 1)
+                        cmax = max(cmax, static_cast<uint32_t>(__shfl_xor(static_cast<int>(cmax), off, 64)));
+                    cmax = __builtin_amdgcn_readfirstlane(cmax);
+#pragma unroll kUnroll
+                    for (uint32_t q = 0; q < cmax; ++q) {
+                        const bool valid = mk != 0ull;
+                        const uint32_t k = valid ? static_cast<uint32_t>(__builtin_ctzll(mk)) : 0u;
+                        mk &= mk - 1ull;
+                        uint32_t idx = k + (k < l0 ? b0 : (k < l0 + l1 ? o1 : o2));
+                        idx = valid ? idx : li;
+                        T xj[3];
+#pragma unroll
+                        for (int d = 0; d < D; ++d)
+                            xj[d] = lpos[d][idx];
+                        visit(idx, valid, Pair<D, T>::r2(xi, xj));
+                    }
+                    continue;
                 }
+                uint32_t mlo = 0, mhi = 0;
+                // candidates in chunks of 32 (the chunk's mask word is
+                // built without a branch)
+                for (uint32_t k0 = 0; k0 < kmax; k0 += 32u) {
+                    const uint32_t kend = min(kmax, k0 + 32u);
+                    uint32_t mw = 0;
+#pragma unroll kUnroll
+                    for (uint32_t k = k0; k < kend; ++k) {
+                        const bool valid = k < tot;
+                        uint32_t idx = k + (k < l0 ? b0 : (k < l0 + l1 ? o1 : o2));
+                        idx = valid ? idx : li;
+                        T xj[3];
+#pragma unroll
+                        for (int d = 0; d < D; ++d)
+                            xj[d] = lpos[d][idx];
+                        T r2;
+                        bool in = Pair<D, T>::inside(a, xi, xj, &r2) && valid;
+                        if (TRANSFER)
+                            in = in && idx != li;
+                        visit(idx, in, r2);
+                        if constexpr (!TRANSFER)
+                            mw |= in ? (1u << (k - k0)) : 0u;
+                    }
+                    if constexpr (!TRANSFER) {
+                        // the particle itself is candidate l0 + (li - b1) of
+                        // its own plane's middle row
+                        if (pzr == planes / 2) {
+                            const uint32_t ks = l0 + (li - b1) - k0;
+                            mw &= (act && ks < 32u) ? ~(1u << ks) : ~0u;
+                        }
+                        acc.cnt += static_cast<uint32_t>(__builtin_popcount(mw));
+                        mlo = k0 == 0u ? mw : mlo;
+                        mhi = k0 == 32u ? mw : mhi;
+                    }
+                }
+                if (!TRANSFER && act)
+                    pmask[i] = tot <= 64u ? ((static_cast<uint64_t>(mhi) << 32) | mlo) : 0ull;
             }
         } else {
 #pragma unroll
