@@ -29,6 +29,11 @@ constexpr int kScanTile = kBlock * kScanItems;
 constexpr int kFinalBlock = 1024;    // threads of the finalize kernel
 // bytes of staged particle data per workgroup of the mass-transfer passes
 // (3-d halos hold three planes of cell rows)
+// LDS staging budget (bytes) of a tile of the mass-transfer passes, per
+// dimension, precision and species count.  The 2-d FP32 kernels and the 3-d
+// FP32 one-species kernels are limited by LDS occupancy and take smaller
+// tiles; FP64 and three-species kernels are limited by registers and take
+// larger ones.
 #ifndef MTPT_LDS_BUDGET_2D
 #define MTPT_LDS_BUDGET_2D 16384
 #endif
@@ -36,10 +41,13 @@ constexpr int kFinalBlock = 1024;    // threads of the finalize kernel
 #define MTPT_LDS_BUDGET_2D_F64 24576
 #endif
 #ifndef MTPT_LDS_BUDGET_3D
-#define MTPT_LDS_BUDGET_3D 46080
+#define MTPT_LDS_BUDGET_3D 30720
 #endif
-template <int D, int PREC> struct LdsBudget {
-    static constexpr int value = D == 3 ? MTPT_LDS_BUDGET_3D
+#ifndef MTPT_LDS_BUDGET_3D_WIDE
+#define MTPT_LDS_BUDGET_3D_WIDE 46080
+#endif
+template <int D, int PREC, int NS> struct LdsBudget {
+    static constexpr int value = D == 3 ? (PREC != 0 && NS == 1 ? MTPT_LDS_BUDGET_3D : MTPT_LDS_BUDGET_3D_WIDE)
                                         : (PREC == 0 ? MTPT_LDS_BUDGET_2D_F64 : MTPT_LDS_BUDGET_2D);
 };
 // unroll factor of the candidate loop of the tiled passes

@@ -33,14 +33,15 @@ template <> struct Types<0> { using T = double; using M = double; using A = doub
 template <> struct Types<1> { using T = float;  using M = double; using A = double; };
 template <> struct Types<2> { using T = float;  using M = float;  using A = float;  };
 
-// particles staged per workgroup (tile cells plus halo): positions, and for
-// the transfer pass also row sums and masses, within the LDS budget
+// Particles a tile (cells plus halo) can stage in LDS: positions, and for the
+// transfer pass also row sums and masses.  Both passes take the capacity of
+// the transfer pass of the same species count, so that the row-sum pass
+// needs no more LDS than its tiles use; it stages positions only.
 template <int D, int PREC, int NS, bool TRANSFER> struct TileCap {
     using T = typename Types<PREC>::T;
     using M = typename Types<PREC>::M;
-    static constexpr int bytes =
-        D * static_cast<int>(sizeof(T)) + (TRANSFER ? static_cast<int>(sizeof(T) + NS * sizeof(M)) : 0);
-    static constexpr int value = LdsBudget<D, PREC>::value / bytes;
+    static constexpr int bytes = D * static_cast<int>(sizeof(T)) + static_cast<int>(sizeof(T) + NS * sizeof(M));
+    static constexpr int value = LdsBudget<D, PREC, NS>::value / bytes;
 };
 
 __device__ __forceinline__ int cell_coord(double x, double glo, double inv, int nc)
@@ -644,6 +645,9 @@ __device__ __forceinline__ void tile_body(const SimArgs& a, uint32_t blk)
     __syncthreads();
 
     const bool use_lds = total <= static_cast<uint32_t>(CAP);
+    // the row-sum pass (one-species instantiation) staged this tile in LDS
+    // too, so it recorded the neighbour masks
+    const bool mask_ok = total <= static_cast<uint32_t>(TileCap<D, PREC, 1, false>::value);
     // cell boundaries of every halo row, as LDS offsets (or global slots)
     for (int idx = tid; idx < nseg * (ncol + 1); idx += kBlock) {
         const int sg = idx / (ncol + 1);
@@ -826,7 +830,7 @@ __device__ __forceinline__ void tile_body(const SimArgs& a, uint32_t blk)
                     }
                 };
                 uint64_t* const pmask = a.cmask + static_cast<size_t>(pzr) * static_cast<size_t>(a.n);
-                if (TRANSFER && kmax <= 64u) {
+                if (TRANSFER && mask_ok && kmax <= 64u) {
                     // neighbours recorded by the row-sum pass: bit k of the
                     // mask is candidate k (same rows, same order) within psi
                     uint64_t mk = act ? pmask[i] : 0ull;
