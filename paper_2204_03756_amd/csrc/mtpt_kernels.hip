@@ -401,32 +401,69 @@ __device__ __forceinline__ void scatter_body(const SimArgs& a, uint32_t blk)
     a.perm[slot] = static_cast<uint32_t>(i);
 }
 
+// Linear cell index of a position (x fastest), as the binning computes it.
+template <int D, typename T>
+__device__ __forceinline__ uint32_t cell_index(const SimArgs& a, const T* v)
+{
+    uint32_t c = 0;
+#pragma unroll
+    for (int k = D - 1; k >= 0; --k)
+        c = c * static_cast<uint32_t>(a.nc[k]) +
+            static_cast<uint32_t>(cell_coord(static_cast<double>(v[k]), a.glo[k], a.inv_side[k], a.nc[k]));
+    return c;
+}
+
 // Slot k holds particle src after the scatter, in arbitrary order inside its
 // cell.  Its final slot is the cell start plus the number of cell members
-// with a smaller (x, pid) key.
+// with a smaller (x, pid) key.  The workgroup gathers the keys of its 256
+// slots once into LDS; only members of a cell that straddles the range of
+// the workgroup are read from global memory.
 template <int D, typename T, typename M>
 __device__ __forceinline__ void place_body(const SimArgs& a, uint32_t blk)
 {
-    const int64_t k = static_cast<int64_t>(blk) * kBlock + threadIdx.x;
-    if (k >= a.n)
-        return;
+    __shared__ T lkx[kBlock];
+    __shared__ uint32_t lkp[kBlock];
+    const int64_t k0 = static_cast<int64_t>(blk) * kBlock;
+    const int64_t k = k0 + threadIdx.x;
+    const bool live = k < a.n;
     const T* xt0 = static_cast<const T*>(a.xt[0]);
-    const uint32_t src = a.perm[k];
-    const uint32_t c = a.cell[src];
+    uint32_t src = 0, kp = 0, c = 0;
+    T xv[3];
+    if (live) {
+        src = a.perm[k];
+#pragma unroll
+        for (int d = 0; d < D; ++d)
+            xv[d] = static_cast<const T*>(a.xt[d])[src];
+        kp = a.pid_src[src];
+        c = cell_index<D, T>(a, xv);
+        lkx[threadIdx.x] = xv[0];
+        lkp[threadIdx.x] = kp;
+    }
+    __syncthreads();
+    if (!live)
+        return;
     const uint32_t b = a.starts[c], e = a.starts[c + 1];
-    const T kx = xt0[src];
-    const uint32_t kp = a.pid_src[src];
+    const uint32_t lo = static_cast<uint32_t>(k0);
+    const uint32_t hi = static_cast<uint32_t>(min(k0 + kBlock, a.n));
+    const T kx = xv[0];
     uint32_t rank = 0;
     for (uint32_t q = b; q < e; ++q) {
-        const uint32_t o = a.perm[q];
-        const T ox = xt0[o];
-        const uint32_t op = a.pid_src[o];
+        T ox;
+        uint32_t op;
+        if (q >= lo && q < hi) {
+            ox = lkx[q - lo];
+            op = lkp[q - lo];
+        } else {
+            const uint32_t o = a.perm[q];
+            ox = xt0[o];
+            op = a.pid_src[o];
+        }
         rank += (ox < kx || (ox == kx && op < kp)) ? 1u : 0u;
     }
     const uint32_t dst = b + rank;
 #pragma unroll
     for (int d = 0; d < D; ++d)
-        static_cast<T*>(a.x[d])[dst] = static_cast<const T*>(a.xt[d])[src];
+        static_cast<T*>(a.x[d])[dst] = xv[d];
     for (int s = 0; s < a.ns; ++s)
         static_cast<M*>(a.m_mid[s])[dst] = static_cast<const M*>(a.m_src[s])[src];
     a.pid_dst[dst] = kp;

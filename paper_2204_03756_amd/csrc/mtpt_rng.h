@@ -28,11 +28,11 @@ __device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1
             k0 += 0x9E3779B9u;
             k1 += 0xBB67AE85u;
         }
-        const uint32_t a0 = 0xD2511F53u * c.x;
-        const uint32_t h0 = __umulhi(0xD2511F53u, c.x);
-        const uint32_t a1 = 0xCD9E8D57u * c.z;
-        const uint32_t h1 = __umulhi(0xCD9E8D57u, c.z);
-        c = make_uint4(h1 ^ c.y ^ k0, a1, h0 ^ c.w ^ k1, a0);
+        // one 32x32->64 product gives both halves
+        const uint64_t p0 = static_cast<uint64_t>(0xD2511F53u) * c.x;
+        const uint64_t p1 = static_cast<uint64_t>(0xCD9E8D57u) * c.z;
+        c = make_uint4(static_cast<uint32_t>(p1 >> 32) ^ c.y ^ k0, static_cast<uint32_t>(p1),
+                       static_cast<uint32_t>(p0 >> 32) ^ c.w ^ k1, static_cast<uint32_t>(p0));
     }
     return c;
 }
