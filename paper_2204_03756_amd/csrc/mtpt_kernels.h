@@ -27,6 +27,7 @@ constexpr int kBlock = 256;          // threads per workgroup, 4 wave64s
 constexpr int kScanItems = 16;       // counts per thread in the scan
 constexpr int kScanTile = kBlock * kScanItems;
 constexpr int kFinalBlock = 1024;    // threads of the finalize kernel
+constexpr uint32_t kScanFold = 2048;  // scans of at most this many tiles skip the top pass
 // bytes of staged particle data per workgroup of the mass-transfer passes
 // (3-d halos hold three planes of cell rows)
 // LDS staging budget (bytes) of a tile of the mass-transfer passes, per
@@ -137,6 +138,7 @@ struct SimArgs {
     uint32_t* pair_part;
     DevStats* st;
     uint32_t scan_blocks;    // ceil((ncells + 1) / kScanTile)
+    int32_t scan_fold;       // scan_blocks <= kScanFold: the down pass sums the block totals itself
     uint32_t part_blocks;    // ceil(n / kBlock)
     int32_t recompute_s;     // the row-sum pass ran this step
     int32_t walk;            // apply the jump in the bin pass (0 at create)

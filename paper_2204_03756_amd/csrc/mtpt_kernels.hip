@@ -343,9 +343,23 @@ __device__ __forceinline__ void scan_top_body(uint32_t* bsum, uint32_t nb)
     }
 }
 
+// bsum holds the exclusive prefix of the tile totals (after the top pass),
+// or with fold the raw totals, summed here over the tiles before blk.
 __device__ __forceinline__ void scan_down_body(uint32_t* in, const uint32_t* in2, uint32_t* out,
-                                               const uint32_t* bsum, uint32_t blk, bool zero_in)
+                                               const uint32_t* bsum, uint32_t blk, bool zero_in,
+                                               bool fold = false)
 {
+    __shared__ uint32_t pre_s;
+    if (fold) {
+        uint32_t t = 0;
+        for (uint32_t b = threadIdx.x; b < blk; b += kBlock)
+            t += bsum[b];
+        t = block_sum<kBlock, uint32_t>(t);
+        if (threadIdx.x == 0)
+            pre_s = t;
+        __syncthreads();
+    }
+    const uint32_t pre = fold ? pre_s : bsum[blk];
     const size_t base = static_cast<size_t>(blk) * kScanTile + threadIdx.x * kScanItems;
     uint4* p = reinterpret_cast<uint4*>(in + base);
     uint32_t v[kScanItems];
@@ -370,7 +384,7 @@ __device__ __forceinline__ void scan_down_body(uint32_t* in, const uint32_t* in2
         s += t;
     }
     uint32_t tot;
-    const uint32_t ex = block_excl_scan(s, &tot) + bsum[blk];
+    const uint32_t ex = block_excl_scan(s, &tot) + pre;
     uint4* o = reinterpret_cast<uint4*>(out + base);
 #pragma unroll
     for (int q = 0; q < kScanItems / 4; ++q)
@@ -1003,6 +1017,7 @@ __device__ __forceinline__ void tile_body(const SimArgs& a, uint32_t blk)
 
 // Totals and pair counters of one step (mode 0) or totals only (mode 1),
 // summed over the per-workgroup partials in a fixed order.
+template <int NT>
 __device__ __forceinline__ void finalize_body(const SimArgs& a, uint32_t nparts, int mode)
 {
     const int ns = a.ns;
@@ -1010,15 +1025,15 @@ __device__ __forceinline__ void finalize_body(const SimArgs& a, uint32_t nparts,
     unsigned long long pairs = 0;
     if (mode == 0 && a.recompute_s) {
         unsigned long long p = 0;
-        for (uint32_t b = threadIdx.x; b < nparts; b += kFinalBlock)
+        for (uint32_t b = threadIdx.x; b < nparts; b += NT)
             p += a.pair_part[b];
-        pairs = block_sum<kFinalBlock, unsigned long long>(p);
+        pairs = block_sum<NT, unsigned long long>(p);
     }
     for (int c = 0; c < ns; ++c) {
         double s = 0.0;
-        for (uint32_t b = threadIdx.x; b < nparts; b += kFinalBlock)
+        for (uint32_t b = threadIdx.x; b < nparts; b += NT)
             s += a.partials[static_cast<size_t>(b) * ns + c];
-        const double t = block_sum<kFinalBlock, double>(s);
+        const double t = block_sum<NT, double>(s);
         if (threadIdx.x == 0) {
             st->totals[c] = t;
             if (!isfinite(t))
@@ -1059,10 +1074,10 @@ __global__ __launch_bounds__(kBlock) void bin_kb(Batch b) { MTPT_BATCH_PROLOGUE;
 
 __global__ __launch_bounds__(kBlock) void scan_reduce_k(SimArgs a) { scan_reduce_body(a.counts, a.tcounts_valid ? a.tcounts : nullptr, a.bsum, blockIdx.x); }
 __global__ __launch_bounds__(kBlock) void scan_reduce_kb(Batch b) { MTPT_BATCH_PROLOGUE; scan_reduce_body(a.counts, a.tcounts_valid ? a.tcounts : nullptr, a.bsum, l); }
-__global__ __launch_bounds__(kBlock) void scan_top_k(SimArgs a) { scan_top_body(a.bsum, a.scan_blocks); }
-__global__ __launch_bounds__(kBlock) void scan_top_kb(Batch b) { MTPT_BATCH_PROLOGUE; (void)l; scan_top_body(a.bsum, a.scan_blocks); }
-__global__ __launch_bounds__(kBlock) void scan_down_k(SimArgs a) { scan_down_body(a.counts, a.tcounts_valid ? a.tcounts : nullptr, a.starts, a.bsum, blockIdx.x, true); }
-__global__ __launch_bounds__(kBlock) void scan_down_kb(Batch b) { MTPT_BATCH_PROLOGUE; scan_down_body(a.counts, a.tcounts_valid ? a.tcounts : nullptr, a.starts, a.bsum, l, true); }
+__global__ __launch_bounds__(kBlock) void scan_top_k(SimArgs a) { if (!a.scan_fold) scan_top_body(a.bsum, a.scan_blocks); }
+__global__ __launch_bounds__(kBlock) void scan_top_kb(Batch b) { MTPT_BATCH_PROLOGUE; (void)l; if (!a.scan_fold) scan_top_body(a.bsum, a.scan_blocks); }
+__global__ __launch_bounds__(kBlock) void scan_down_k(SimArgs a) { scan_down_body(a.counts, a.tcounts_valid ? a.tcounts : nullptr, a.starts, a.bsum, blockIdx.x, true, a.scan_fold != 0); }
+__global__ __launch_bounds__(kBlock) void scan_down_kb(Batch b) { MTPT_BATCH_PROLOGUE; scan_down_body(a.counts, a.tcounts_valid ? a.tcounts : nullptr, a.starts, a.bsum, l, true, a.scan_fold != 0); }
 __global__ __launch_bounds__(kBlock) void scatter_k(SimArgs a) { scatter_body(a, xcd_block(blockIdx.x, gridDim.x)); }
 __global__ __launch_bounds__(kBlock) void scatter_kb(Batch b) { MTPT_BATCH_PROLOGUE; scatter_body(a, l); }
 
@@ -1090,13 +1105,13 @@ __global__ __launch_bounds__(kBlock) void transfer_kb(Batch b) { MTPT_BATCH_PROL
 
 __global__ __launch_bounds__(kFinalBlock) void finalize_k(SimArgs a, uint32_t nparts, int mode)
 {
-    finalize_body(a, nparts, mode);
+    finalize_body<kFinalBlock>(a, nparts, mode);
 }
 __global__ __launch_bounds__(kFinalBlock) void finalize_kb(Batch b)
 {
     MTPT_BATCH_PROLOGUE;
     (void)l;
-    finalize_body(a, a.ntiles, 0);
+    finalize_body<kFinalBlock>(a, a.ntiles, 0);
 }
 
 #undef MTPT_BATCH_PROLOGUE

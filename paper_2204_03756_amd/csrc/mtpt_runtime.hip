@@ -370,6 +370,7 @@ SimArgs base_args(const mtpt_sim* s)
     a.pair_part = s->pair_part;
     a.st = s->st;
     a.scan_blocks = q.scan_blocks;
+    a.scan_fold = q.scan_blocks <= kScanFold ? 1 : 0;
     a.part_blocks = q.part_blocks;
     return a;
 }
@@ -437,6 +438,8 @@ int enqueue_binning(mtpt_sim* s, const SimArgs& a, bool with_bin)
                                  PH_SCATTER, PH_PLACE};
     for (int ph : phases) {
         if (ph == PH_BIN && !with_bin)
+            continue;
+        if (ph == PH_SCAN_TOP && a.scan_fold)
             continue;
         const int rc = launch(s, ph, a);
         if (rc)
@@ -1086,12 +1089,17 @@ int mtpt_pool_tick(mtpt_pool* p, int32_t* n_completed)
             const SimArgs* dargs = reinterpret_cast<const SimArgs*>(d + goff[gi]);
             const uint32_t* dpre = reinterpret_cast<const uint32_t*>(d + align_up(goff[gi] + ns * sizeof(SimArgs), 256));
             const uint32_t* hpre = reinterpret_cast<const uint32_t*>(h + align_up(goff[gi] + ns * sizeof(SimArgs), 256));
+            const SimArgs* hargs = reinterpret_cast<const SimArgs*>(h + goff[gi]);
+            bool any_unfolded = false;
+            for (size_t i = 0; i < ns; ++i)
+                any_unfolded = any_unfolded || !hargs[i].scan_fold;
             std::vector<int> phases;
             if (k.bin)
                 phases.push_back(PH_BIN);
             if (k.moving)
                 for (int ph : {PH_SCAN_REDUCE, PH_SCAN_TOP, PH_SCAN_DOWN, PH_SCATTER, PH_PLACE})
-                    phases.push_back(ph);
+                    if (ph != PH_SCAN_TOP || any_unfolded)
+                        phases.push_back(ph);
             if (k.rowsum)
                 phases.push_back(PH_ROWSUM);
             phases.push_back(PH_TRANSFER);
