@@ -218,6 +218,23 @@ def test_rw2d_full_size_first_steps(mt, oracle):
     say(f"  rw2d 100 steps: drift {st['drift']:.3e}, pairs/step {st['pairs_last']}")
 
 
+@pytest.mark.parametrize("prec", [W.FP64, W.FP32W_FP64ACC])
+def test_sparse_grid_many_scan_tiles(mt, oracle, prec):
+    """3e6 particles with a tiny psi: the grid reaches its cap of ~4 cells
+    per particle (over 2048 scan tiles, so the scan takes its top pass), the
+    cells are smaller than a jump (most walked particles leave their tile and
+    take the global-histogram slots), and a tile holds few particles."""
+    n = 3_000_000
+    L = math.sqrt(n)
+    p = W.Params(dim=2, n=n, lo=[0.0, 0.0, 0.0], hi=[L, L, 0.0], d_rw=0.5, d_mt=0.002, dt=0.1,
+                 beta=0.5, psi=0.0, seed=0x4D54505409, precision=prec)
+    x = W._uniform(20220409, n, 2, p.lo, p.hi)
+    m = np.random.default_rng(9).random((1, n))
+    w = W.Workload("sparse2d", p, x, m, 3, {})
+    m_, x_, st, ref = check_parity(mt, oracle, w, 3)
+    assert st["n_cells"] + 1 > 2048 * 4096
+
+
 def test_rw3d_full_size_first_step(mt, oracle):
     w = W.rw3d(precision=W.FP32W_FP64ACC)
     check_parity(mt, oracle, w, 1)
