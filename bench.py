@@ -193,7 +193,7 @@ def cpu_baseline(W, seconds_hint: float = 20.0):
     from oracle import oracle as O
     threads = O.max_threads()
     w = W.rw2d(precision=W.FP32W_FP64ACC)
-    steps = 2
+    steps = 5
     t0 = time.perf_counter()
     r = O.run(w.params, w.x0, w.m0, steps, threads=threads)
     dt = time.perf_counter() - t0
