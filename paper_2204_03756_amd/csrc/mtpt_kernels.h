@@ -120,6 +120,7 @@ struct SimArgs {
     // buffers
     void* x[3];
     void* xt[3];
+    void* jmp[3];            // next step's jumps (type of the positions), sorted order
     void* m_src[3];          // gather source (old order)
     void* m_mid[3];          // masses in the current sorted order
     void* m_dst[3];          // transfer output

@@ -161,6 +161,36 @@ __device__ __forceinline__ float walk_reflect<float>(float x, double z, double s
     return v;
 }
 
+// The jump of one coordinate in the type of the positions (the FP64
+// product z sdev, rounded once for FP32 positions) and the reflected
+// position; walk_reflect is the two in one.
+template <typename T>
+__device__ __forceinline__ T jump_of(double z, double sdev)
+{
+#pragma clang fp contract(off)
+    return static_cast<T>(z * sdev);
+}
+template <typename T>
+__device__ __forceinline__ T reflect_jump(T x, T jump, double lo, double hi, float lof, float hif);
+template <>
+__device__ __forceinline__ double reflect_jump<double>(double x, double jump, double lo, double hi, float, float)
+{
+#pragma clang fp contract(off)
+    double v = x + jump;
+    while (v < lo || v > hi)
+        v = (v < lo) ? 2.0 * lo - v : 2.0 * hi - v;
+    return v;
+}
+template <>
+__device__ __forceinline__ float reflect_jump<float>(float x, float jump, double, double, float lof, float hif)
+{
+#pragma clang fp contract(off)
+    float v = x + jump;
+    while (v < lof || v > hif)
+        v = (v < lof) ? 2.0f * lof - v : 2.0f * hif - v;
+    return v;
+}
+
 // x-window [x_i - win, x_i + win] in the type of the positions, rounded
 // outward so that no x within the exact window falls outside it
 template <typename T> struct Window;
@@ -481,6 +511,17 @@ __device__ __forceinline__ void place_body(const SimArgs& a, uint32_t blk)
     for (int s = 0; s < a.ns; ++s)
         static_cast<M*>(a.m_mid[s])[dst] = static_cast<const M*>(a.m_src[s])[src];
     a.pid_dst[dst] = kp;
+    if (a.fuse_bin) {
+        // the jumps of the step after a.step, for the transfer pass's walk
+        // (this pass waits on memory; the arithmetic is hidden there)
+        double z[3], spare;
+        normal_pair(a.seed, a.step + 1, kp, 0u, &z[0], &z[1]);
+        if (D == 3)
+            normal_pair(a.seed, a.step + 1, kp, 1u, &z[2], &spare);
+#pragma unroll
+        for (int d = 0; d < D; ++d)
+            static_cast<T*>(a.jmp[d])[dst] = jump_of<T>(z[d], a.sdev);
+    }
 }
 
 // ------------------------------------------------------------ tiled passes
@@ -586,8 +627,9 @@ __device__ __forceinline__ void scan_row(const SimArgs& a, PX p, PS sr, PM ms, u
     }
 }
 
-// Walk, cell id and histogram slot of sorted particle i for the step after
-// a.step (the next step's binning, done while its position is in registers).
+// Walk (with the jumps the place pass drew), cell id and histogram slot of
+// sorted particle i for the step after a.step (the next step's binning,
+// done while its position is in registers).
 // A particle that stays inside the tile (cells [tlo, thi) per axis) takes
 // its slot from the tile's LDS histogram hist; one that leaves takes it from
 // the global histogram, flagged in bit 31 of its rank.
@@ -595,16 +637,12 @@ template <int D, typename T>
 __device__ __forceinline__ void bin_next(const SimArgs& a, uint32_t i, const T* x, const int* tlo,
                                          const int* thi, uint32_t* hist)
 {
-    const uint32_t pid = a.pid_dst[i];
-    double z[3], spare;
-    normal_pair(a.seed, a.step + 1, pid, 0u, &z[0], &z[1]);
-    if (D == 3)
-        normal_pair(a.seed, a.step + 1, pid, 1u, &z[2], &spare);
     uint32_t c = 0, lc = 0;
     bool inside = true;
 #pragma unroll
     for (int k = D - 1; k >= 0; --k) {
-        const T v = walk_reflect<T>(x[k], z[k], a.sdev, a.lo[k], a.hi[k], a.lof[k], a.hif[k]);
+        const T v = reflect_jump<T>(x[k], static_cast<const T*>(a.jmp[k])[i], a.lo[k], a.hi[k], a.lof[k],
+                                    a.hif[k]);
         static_cast<T*>(a.xt[k])[i] = v;
         const int ck = cell_coord(static_cast<double>(v), a.glo[k], a.inv_side[k], a.nc[k]);
         c = c * static_cast<uint32_t>(a.nc[k]) + static_cast<uint32_t>(ck);

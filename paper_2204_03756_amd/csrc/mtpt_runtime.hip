@@ -87,7 +87,7 @@ struct Plan {
     bool trim_rows = false;
     size_t tsz = 8, msz = 8;
     size_t off_x[3]{}, off_xt[3]{}, off_m[2][3]{}, off_p[2]{}, off_s = 0, off_cell = 0, off_rank = 0,
-           off_perm = 0, off_cmask = 0, off_counts = 0, off_tcounts = 0, off_starts = 0, off_bsum = 0, off_part = 0, off_pair = 0,
+           off_perm = 0, off_jmp[3]{}, off_cmask = 0, off_counts = 0, off_tcounts = 0, off_starts = 0, off_bsum = 0, off_part = 0, off_pair = 0,
            off_stats = 0;
     size_t bytes = 0;
 };
@@ -205,6 +205,8 @@ Plan make_plan(const mtpt_params& p)
         q.off_x[k] = k < q.dim ? take(n * q.tsz) : 0;
     for (int k = 0; k < 3; ++k)
         q.off_xt[k] = k < q.dim ? take(n * q.tsz) : 0;
+    for (int k = 0; k < 3; ++k)
+        q.off_jmp[k] = k < q.dim ? take(n * q.tsz) : 0;
     for (int b = 0; b < 2; ++b)
         for (int c = 0; c < 3; ++c)
             q.off_m[b][c] = c < q.ns ? take(n * q.msz) : 0;
@@ -243,6 +245,7 @@ struct mtpt_sim {
     char* base = nullptr;
     void* X[3]{};
     void* XT[3]{};
+    void* J[3]{};
     void* M[2][3]{};
     uint32_t* P[2]{};
     void* S = nullptr;
@@ -275,6 +278,7 @@ void carve(mtpt_sim* s)
     for (int k = 0; k < 3; ++k) {
         s->X[k] = k < q.dim ? b + q.off_x[k] : nullptr;
         s->XT[k] = k < q.dim ? b + q.off_xt[k] : nullptr;
+        s->J[k] = k < q.dim ? b + q.off_jmp[k] : nullptr;
     }
     for (int bb = 0; bb < 2; ++bb)
         for (int c = 0; c < 3; ++c)
@@ -356,6 +360,7 @@ SimArgs base_args(const mtpt_sim* s)
     for (int k = 0; k < 3; ++k) {
         a.x[k] = s->X[k];
         a.xt[k] = s->XT[k];
+        a.jmp[k] = s->J[k];
     }
     a.srow = s->S;
     a.cell = s->cell;
