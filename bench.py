@@ -29,20 +29,23 @@ def algorithmic_bytes(kernel: str, n: int, dim: int, ns: int, tsz: int, msz: int
     """Bytes each launch must move at minimum (one read of every input it
     needs, one write of every output), per the data layout of the path."""
     pos = dim * tsz
-    walk = 4 + pos + 4 + 4                         # pid in; walked x, cell, slot out
+    masks = 8 * (3 if dim == 3 else 1)             # neighbour bits per particle and plane
     per = {
-        "bin": pos + walk,                         # x in + the walk
+        # x, pid in; walked x, cell, slot out
+        "bin": pos + 4 + pos + 4 + 4,
         "scatter": 4 + 4 + 4,                      # cell, rank in; perm out
-        # perm, cell, x, m, pid of the slot's particle in; x, m, pid out
-        "place": 4 + 4 + pos + ns * msz + 4 + pos + ns * msz + 4,
-        "rowsum": pos + tsz,                       # x in; s out
-        # x, s, m in; m out; then the next step's walk of the same particle
-        "transfer": pos + tsz + ns * msz + ns * msz + walk,
+        # perm, x, m, pid of the slot's particle in; x, m, pid and the next
+        # step's jumps out
+        "place": 4 + pos + ns * msz + 4 + pos + ns * msz + 4 + pos,
+        "rowsum": pos + tsz + masks,               # x in; s and masks out
+        # x, s, m, masks in; m out; then the next step's walk of the same
+        # particle: jumps in, walked x, cell, slot out
+        "transfer": pos + tsz + ns * msz + masks + ns * msz + pos + pos + 4 + 4,
     }
     if kernel in ("scan_reduce",):
-        return ncells * 4.0
+        return ncells * 8.0                        # both count arrays
     if kernel in ("scan_down",):
-        return ncells * 12.0
+        return ncells * 16.0                       # both counts in; starts out; counts cleared
     return float(per.get(kernel, 0) * n)
 
 
@@ -89,31 +92,31 @@ def run_path(mt, W, precision: int, steps: int, warmup: int, profile_steps: int 
     }
 
 
-# Algorithmic VALU lane-slots (one slot = one lane of one full-rate VALU
-# instruction; transcendentals count 4, FP64 arithmetic 2), per ordered pair
-# within psi and per particle, of the two ALU-bound passes:
+# Algorithmic VALU lane-slots (one slot = one lane of one VALU instruction at
+# the issue rate: FP32 without packing and FP64 alike; transcendentals count
+# 4), per ordered pair within psi and per particle, of the two ALU-bound
+# passes:
 #   rowsum   r^2 (2d), cutoff test, scale, exp (4), add            = 2d + 7
 #   transfer the same K (2d + 6), W = 2K rcp(s_i + s_j) (7), and per
-#            species the increment (FP32W: FP64 sub, cvt, FP64 fma = 5;
-#            Kahan: 8 FP32 ops; FP64: 6)                           = 2d + 13 + c S
-#   walk     (fused into transfer) per particle and Philox call: Philox4x32-10
-#            (~100 integer ops) + Box-Muller in FP64 (~125 ops = 250 slots)
-#            + reflect/cell (~30): 380, two calls in 3-d
-# The FP64 path's pair terms are doubled (FP64 at half rate) plus 40 for the
-# FP64 exp and 40 for the FP64 divide.
+#            species the increment (FP32W: FP64 sub, cvt, FP64 fma = 3;
+#            Kahan: 6 FP32 ops)                                     = 2d + 13 + c S
+#   FP64     rowsum: canonical r^2 (3d - 1), test, exp (~25), add  = 3d + 26
+#            transfer: the same K, W with an FP64 divide (~12), per
+#            species sub and fma (2)                                = 3d + 38 + 2 S
+#   walk     per particle in the transfer pass: jump add, reflection test
+#            and cell index, 10 per dimension (the generator runs in the
+#            place pass)
 def algorithmic_slots(kernel: str, n: int, pairs: int, dim: int, ns: int, prec: str) -> float:
-    walk = 380.0 * (2 if dim == 3 else 1)
-    per_species = {"fp32w": 5.0, "kahan": 8.0, "fp64": 6.0}[prec]
+    walk = 10.0 * dim
     if kernel == "rowsum":
-        per = 2 * dim + 7.0
-        if prec == "fp64":
-            per = 2 * per + 40.0
+        per = 3 * dim + 26.0 if prec == "fp64" else 2 * dim + 7.0
         return pairs * per
     if kernel == "transfer":
-        per = 2 * dim + 13.0
         if prec == "fp64":
-            per = 2 * per + 80.0
-        return pairs * (per + per_species * ns) + n * walk
+            per = 3 * dim + 38.0 + 2.0 * ns
+        else:
+            per = 2 * dim + 13.0 + {"fp32w": 3.0, "kahan": 6.0}[prec] * ns
+        return pairs * per + n * walk
     return 0.0
 
 
@@ -126,19 +129,21 @@ def roofline(res, dim, ns, tsz, msz, n, prec="fp32w"):
     avg_s = ms_total / launches / 1e3
     common = {"kernel": name, "avg_launch_us": round(avg_s * 1e6, 2),
               "phase_ms_per_step": {k: round(v[0] / v[1], 4) for k, v in phases.items()}}
-    if name in ("rowsum", "transfer"):
-        slots = algorithmic_slots(name, n, res["pairs_per_step"], dim, ns, prec)
-        achieved = slots / avg_s / 1e9
-        return {**common, "bound": "alu", "achieved": round(achieved, 1), "peak": VALU_PEAK_GOPS,
-                "unit": "Gop/s", "frac": round(achieved / VALU_PEAK_GOPS, 4), "traffic": None,
-                "ops_per_launch": slots,
-                "hbm_algorithmic_GBps": round(algorithmic_bytes(name, n, dim, ns, tsz, msz,
-                                                                res["n_cells"]) / avg_s / 1e9, 1)}
     byt = algorithmic_bytes(name, n, dim, ns, tsz, msz, res["n_cells"])
-    achieved = byt / avg_s / 1e9
-    return {**common, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-            "bytes_per_launch": byt}
+    hbm = byt / avg_s / 1e9
+    out = {**common, "bound": "hbm", "achieved": round(hbm, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": round(hbm / HBM_PEAK_GBS, 4), "traffic": None, "bytes_per_launch": byt}
+    if name in ("rowsum", "transfer"):
+        # both rooflines; the bound is the one with the longer ideal time
+        slots = algorithmic_slots(name, n, res["pairs_per_step"], dim, ns, prec)
+        alu = slots / avg_s / 1e9
+        out["ops_per_launch"] = slots
+        out["alu_frac"] = round(alu / VALU_PEAK_GOPS, 4)
+        out["hbm_frac"] = round(hbm / HBM_PEAK_GBS, 4)
+        if alu / VALU_PEAK_GOPS > hbm / HBM_PEAK_GBS:
+            out.update({"bound": "alu", "achieved": round(alu, 1), "peak": VALU_PEAK_GOPS,
+                        "unit": "Gop/s", "frac": round(alu / VALU_PEAK_GOPS, 4)})
+    return out
 
 
 def source_sha256() -> str:
