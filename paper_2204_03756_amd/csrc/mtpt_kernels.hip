@@ -675,6 +675,10 @@ __device__ __forceinline__ void tile_body(const SimArgs& a, uint32_t blk)
     __shared__ uint32_t cst[kSegs][TileLimits<D>::cols];
     __shared__ uint32_t own_gb[kRows];
     __shared__ uint32_t own_pre[kRows + 1];
+    // the row table and row-wise staging, except in the 3-d three-species
+    // transfer pass (their registers would cost it a wave per SIMD)
+    constexpr bool kLean = !(D == 3 && NS == 3 && TRANSFER);
+    __shared__ uint8_t row_of[kLean ? CAP : 1];   // own row of each own particle
     constexpr int kHist = TRANSFER ? TileLimits<D>::max_x * TileLimits<D>::max_y : 1;
     __shared__ uint32_t hist[kHist];
 
@@ -752,17 +756,15 @@ __device__ __forceinline__ void tile_body(const SimArgs& a, uint32_t blk)
         }
         cst[sg][c] = v;
     }
+    // own row of every own particle, when they fit the table
+    const bool rows_tab = kLean && own_total <= static_cast<uint32_t>(CAP);
+    if (rows_tab)
+        for (int r = tid >> 6; r < nrow; r += kBlock / 64)
+            for (uint32_t j = static_cast<uint32_t>(tid & 63); j < own_pre[r + 1] - own_pre[r]; j += 64)
+                row_of[own_pre[r] + j] = static_cast<uint8_t>(r);
     if (use_lds) {
-        for (uint32_t idx = tid; idx < total; idx += kBlock) {
-            int lo = 0, hi = nseg - 1;
-            while (lo < hi) {
-                const int mid = (lo + hi + 1) >> 1;
-                if (seg_off[mid] <= idx)
-                    lo = mid;
-                else
-                    hi = mid - 1;
-            }
-            const uint32_t g = seg_gb[lo] + (idx - seg_off[lo]);
+        // each halo row is one contiguous run in HBM and in LDS
+        auto stage = [&](uint32_t idx, uint32_t g) {
 #pragma unroll
             for (int d = 0; d < D; ++d)
                 lpos[d][idx] = static_cast<const T*>(a.x[d])[g];
@@ -771,6 +773,26 @@ __device__ __forceinline__ void tile_body(const SimArgs& a, uint32_t blk)
 #pragma unroll
                 for (int c = 0; c < NS; ++c)
                     lms[c][idx] = static_cast<const M*>(a.m_mid[c])[g];
+            }
+        };
+        if (kLean && total >= 48u * static_cast<uint32_t>(nseg)) {
+            // long rows: a wave copies whole rows
+            const uint32_t lane = static_cast<uint32_t>(tid & 63);
+            for (int sg = tid >> 6; sg < nseg; sg += kBlock / 64)
+                for (uint32_t j = lane; j < seg_off[sg + 1] - seg_off[sg]; j += 64)
+                    stage(seg_off[sg] + j, seg_gb[sg] + j);
+        } else {
+            // short rows: every thread takes the next slot and finds its row
+            for (uint32_t idx = tid; idx < total; idx += kBlock) {
+                int lo = 0, hi = nseg - 1;
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (seg_off[mid] <= idx)
+                        lo = mid;
+                    else
+                        hi = mid - 1;
+                }
+                stage(idx, seg_gb[lo] + (idx - seg_off[lo]));
             }
         }
     }
@@ -787,13 +809,18 @@ __device__ __forceinline__ void tile_body(const SimArgs& a, uint32_t blk)
         const uint32_t t = base + tid;
         const bool act = t < own_total;
         const uint32_t tt = act ? t : own_total - 1u;
-        int r = 0, hi = nrow - 1;
-        while (r < hi) {
-            const int mid = (r + hi + 1) >> 1;
-            if (own_pre[mid] <= tt)
-                r = mid;
-            else
-                hi = mid - 1;
+        int r = 0;
+        if (rows_tab) {
+            r = row_of[kLean ? tt : 0u];
+        } else {
+            int hi = nrow - 1;
+            while (r < hi) {
+                const int mid = (r + hi + 1) >> 1;
+                if (own_pre[mid] <= tt)
+                    r = mid;
+                else
+                    hi = mid - 1;
+            }
         }
         const uint32_t i = own_gb[r] + (tt - own_pre[r]);
         T xi[3];
@@ -1136,10 +1163,12 @@ __global__ __launch_bounds__(kBlock) void rowsum_k(SimArgs a) { tile_body<D, PRE
 template <int D, int PREC>
 __global__ __launch_bounds__(kBlock) void rowsum_kb(Batch b) { MTPT_BATCH_PROLOGUE; tile_body<D, PREC, 1, false>(a, l); }
 
+// the 2-d FP64 one-species transfer kernel is held to the registers of 5
+// workgroups per CU, which its LDS allows
 template <int D, int PREC, int NS>
-__global__ __launch_bounds__(kBlock) void transfer_k(SimArgs a) { tile_body<D, PREC, NS, true>(a, xcd_block(blockIdx.x, gridDim.x)); }
+__global__ __launch_bounds__(kBlock, PREC == 0 && D == 2 && NS == 1 ? 5 : 1) void transfer_k(SimArgs a) { tile_body<D, PREC, NS, true>(a, xcd_block(blockIdx.x, gridDim.x)); }
 template <int D, int PREC, int NS>
-__global__ __launch_bounds__(kBlock) void transfer_kb(Batch b) { MTPT_BATCH_PROLOGUE; tile_body<D, PREC, NS, true>(a, l); }
+__global__ __launch_bounds__(kBlock, PREC == 0 && D == 2 && NS == 1 ? 5 : 1) void transfer_kb(Batch b) { MTPT_BATCH_PROLOGUE; tile_body<D, PREC, NS, true>(a, l); }
 
 __global__ __launch_bounds__(kFinalBlock) void finalize_k(SimArgs a, uint32_t nparts, int mode)
 {
