@@ -187,6 +187,16 @@ def test_edge_cases(mt, oracle):
     xs = rng.random((500, 2)) * 3.0
     cases.append(("one-cell", W.Params(dim=2, n=500, lo=[0, 0, 0], hi=[3, 3, 0], d_rw=0.2, d_mt=2.0,
                                        dt=0.5, seed=9), xs, rng.random((1, 500))))
+    # 3000 particles in one cell: the tile overflows the LDS capacity of every
+    # path, so both passes read their rows from global memory
+    xc = rng.random((3000, 2)) * 2.0
+    cases.append(("cluster", W.Params(dim=2, n=3000, lo=[0, 0, 0], hi=[2, 2, 0], d_rw=0.1, d_mt=2.0,
+                                      dt=0.5, seed=13), xc, rng.random((1, 3000))))
+    # ~20 particles per cell in 3-d: a plane's candidate rows hold more than
+    # 64 particles, so the transfer pass takes the full candidate loop
+    xd = rng.random((4320, 3)) * 6.0
+    cases.append(("dense3d", W.Params(dim=3, n=4320, lo=[0, 0, 0], hi=[6, 6, 6], d_rw=0.05, d_mt=1.0 / 3.6,
+                                      dt=0.1, seed=17), xd, rng.random((1, 4320))))
     xr = rng.random((4097 + 257, 3)) * [20, 7, 9]
     cases.append(("ragged", W.Params(dim=3, n=len(xr), lo=[0, 0, 0], hi=[20, 7, 9], d_rw=0.3, d_mt=0.6,
                                      dt=0.1, seed=11), xr, rng.random((1, len(xr)))))
