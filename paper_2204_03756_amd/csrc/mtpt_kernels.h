@@ -7,11 +7,14 @@
 //                    numbered x fastest) and inside a cell by (x, pid), so
 //                    every row of cells is one x-sorted run of the arrays
 //   XT[k][n]    T    walked positions in the order before re-binning
+//   J[k][n]     T    the next step's jumps, sorted order (drawn by place)
 //   M[2][S][n]  M    masses, two buffers (Jacobi update)
 //   P[2][n]     u32  pid of each sorted slot, two buffers
 //   Srow[n]     T    row sums s_i = sum_j K_ij
-//   cell, rank, perm [n] u32   binning scratch
-//   counts[], starts[] u32     cell histogram and offsets (tile-padded)
+//   cmask[pl][n] u64 neighbour bits of the candidate rows, per plane
+//   cell, rank, perm [n] u32   binning scratch (rank bit 31: left its tile)
+//   counts[], tcounts[], starts[] u32   cell histograms (global atomics;
+//                    per-tile stores) and offsets, tile-padded
 //   bsum[]      u32  per-tile partial sums of the scan
 //   partials[]  f64  per-workgroup mass partial sums [parts][S]
 //   pair_part[] u32  per-workgroup pair counts
@@ -51,6 +54,11 @@ template <int D, int PREC, int NS> struct LdsBudget {
     static constexpr int value = D == 3 ? (PREC != 0 && NS == 1 ? MTPT_LDS_BUDGET_3D : MTPT_LDS_BUDGET_3D_WIDE)
                                         : (PREC == 0 ? MTPT_LDS_BUDGET_2D_F64 : MTPT_LDS_BUDGET_2D);
 };
+// the 2-d FP64 row-sum pass hands its own cells to lanes in order of their
+// candidate count
+#ifndef MTPT_CELL_ORDER_2D
+#define MTPT_CELL_ORDER_2D 1
+#endif
 // unroll factor of the candidate loop of the tiled passes
 #ifndef MTPT_CAND_UNROLL_2D
 #define MTPT_CAND_UNROLL_2D 1
@@ -121,7 +129,7 @@ struct SimArgs {
     void* x[3];
     void* xt[3];
     void* jmp[3];            // next step's jumps (type of the positions), sorted order
-    void* m_src[3];          // gather source (old order)
+    void* m_src[3];          // masses in the order before re-binning (place source)
     void* m_mid[3];          // masses in the current sorted order
     void* m_dst[3];          // transfer output
     uint32_t* pid_src;
@@ -129,7 +137,7 @@ struct SimArgs {
     void* srow;
     uint32_t* cell;
     uint32_t* rank;
-    uint32_t* perm;
+    uint32_t* perm;          // slot -> particle of the order before re-binning
     uint32_t* counts;        // per-cell histogram filled with global atomics
     uint32_t* tcounts;       // per-cell counts of particles that stayed in their tile
     uint64_t* cmask;         // [plane][n] neighbour bits of the candidate rows (row-sum pass)

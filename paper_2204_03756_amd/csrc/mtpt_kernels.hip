@@ -679,6 +679,15 @@ __device__ __forceinline__ void tile_body(const SimArgs& a, uint32_t blk)
     // transfer pass (their registers would cost it a wave per SIMD)
     constexpr bool kLean = !(D == 3 && NS == 3 && TRANSFER);
     __shared__ uint8_t row_of[kLean ? CAP : 1];   // own row of each own particle
+    // 2-d FP64 row-sum pass: own cells in order of their candidate count, so
+    // that a wave's trip count is near its lanes' mean (the pass's only sum
+    // over particles, the pair count, is an integer: the order changes no
+    // result).  The FP32 pass's candidates are too cheap to repay the ordering.
+    constexpr bool kCellOrder = D == 2 && PREC == 0 && !TRANSFER && MTPT_CELL_ORDER_2D != 0;
+    constexpr int kCells = kCellOrder ? TileLimits<D>::max_x * TileLimits<D>::max_y : 1;
+    __shared__ uint16_t ord[kCellOrder ? CAP : 1];
+    __shared__ uint8_t ckey[kCells];
+    __shared__ uint32_t obase[64];
     constexpr int kHist = TRANSFER ? TileLimits<D>::max_x * TileLimits<D>::max_y : 1;
     __shared__ uint32_t hist[kHist];
 
@@ -798,6 +807,48 @@ __device__ __forceinline__ void tile_body(const SimArgs& a, uint32_t blk)
     }
     __syncthreads();
 
+    const bool cell_order = kCellOrder && use_lds && rows_tab;
+    if constexpr (kCellOrder) {
+        if (cell_order) {
+            if (tid < 64)
+                obase[tid] = 0;
+            __syncthreads();
+            // own row r is halo row r + 1; own column cx is staged column x0 - xa + cx
+            for (int j = tid; j < tw * nrow; j += kBlock) {
+                const int r = j / tw;
+                const int cxr = x0 - xa + (j - r * tw);
+                const int cl = cxr > 0 ? cxr - 1 : 0;
+                const int ch = cxr + 2 < ncol ? cxr + 2 : ncol;
+                uint32_t tot = 0;
+#pragma unroll
+                for (int q = 0; q < 3; ++q)
+                    tot += cst[r + q][ch] - cst[r + q][cl];
+                const uint32_t key = min(tot, 63u);
+                ckey[j] = static_cast<uint8_t>(key);
+                atomicAdd(&obase[key], cst[r + 1][cxr + 1] - cst[r + 1][cxr]);
+            }
+            __syncthreads();
+            if (tid < 64) {
+                const uint32_t v = obase[tid];
+                obase[tid] = wave_incl_scan(v) - v;
+            }
+            __syncthreads();
+            for (int j = tid; j < tw * nrow; j += kBlock) {
+                const int r = j / tw;
+                const int cxr = x0 - xa + (j - r * tw);
+                const uint32_t c0 = cst[r + 1][cxr];
+                const uint32_t nin = cst[r + 1][cxr + 1] - c0;
+                if (nin == 0)
+                    continue;
+                const uint32_t pos = atomicAdd(&obase[ckey[j]], nin);
+                const uint32_t t0 = own_pre[r] + (c0 - cst[r + 1][x0 - xa]);
+                for (uint32_t q = 0; q < nin; ++q)
+                    ord[pos + q] = static_cast<uint16_t>(t0 + q);
+            }
+            __syncthreads();
+        }
+    }
+
     uint32_t pairs = 0;
     double msum[NS];
 #pragma unroll
@@ -808,7 +859,11 @@ __device__ __forceinline__ void tile_body(const SimArgs& a, uint32_t blk)
     for (uint32_t base = 0; base < own_total; base += kBlock) {
         const uint32_t t = base + tid;
         const bool act = t < own_total;
-        const uint32_t tt = act ? t : own_total - 1u;
+        uint32_t tt = act ? t : own_total - 1u;
+        if constexpr (kCellOrder) {
+            if (cell_order)
+                tt = ord[tt];
+        }
         int r = 0;
         if (rows_tab) {
             r = row_of[kLean ? tt : 0u];
@@ -823,10 +878,14 @@ __device__ __forceinline__ void tile_body(const SimArgs& a, uint32_t blk)
             }
         }
         const uint32_t i = own_gb[r] + (tt - own_pre[r]);
+        // the particle's LDS slot; its own position from there when the lanes
+        // are permuted (cell order), else a coalesced global load
+        const int smid0 = (planes == 3 ? rows : 0) + r + 1;
+        const uint32_t lself = i - seg_gb[smid0] + seg_off[smid0];
         T xi[3];
 #pragma unroll
         for (int d = 0; d < D; ++d)
-            xi[d] = static_cast<const T*>(a.x[d])[i];
+            xi[d] = cell_order ? lpos[d][lself] : static_cast<const T*>(a.x[d])[i];
         const int cxr = cell_coord(static_cast<double>(xi[0]), a.glo[0], a.inv_side[0], nc0) - xa;
         const int cl = cxr > 0 ? cxr - 1 : 0;
         const int ch = cxr + 2 < ncol ? cxr + 2 : ncol;
@@ -842,8 +901,7 @@ __device__ __forceinline__ void tile_body(const SimArgs& a, uint32_t blk)
         }
         if (use_lds) {
             // LDS slot of particle i itself (the self pair is skipped by slot)
-            const int smid = (planes == 3 ? rows : 0) + r + 1;
-            const uint32_t li = i - seg_gb[smid] + seg_off[smid];
+            const uint32_t li = lself;
             if constexpr (!TRANSFER)
                 acc.cnt = 1;   // self; the neighbours are counted from the masks
             // distances from the particle to the y (and z) slabs of the rows
