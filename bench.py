@@ -239,6 +239,8 @@ WORKLOAD_TEXT = {
             "psi=3*sqrt(4*D_MT*dt), 100 steps, 1000-particle central source",
     "react3d": "react3d: 3-d MTPT, N=3.2e7 in [0,318]^3, D_RW=0.3, D_MT=0.7, dt=0.05, 200 steps, "
                "A+B->C mass-based reaction after each transfer, k=1",
+    "adv2d": "adv2d: rw2d with a drift velocity v=(1, 0.5) (advection-dispersion), N=4e6 in "
+             "[0,2000]^2, 100 steps",
 }
 
 
@@ -249,7 +251,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
-    ap.add_argument("--workload", default="rw2d", choices=["rw2d", "rw3d", "react3d", "serve"],
+    ap.add_argument("--workload", default="rw2d", choices=["rw2d", "rw3d", "react3d", "adv2d", "serve"],
                     help="rw2d is the benchmark line; the others are reported the same way")
     ap.add_argument("--requests", type=int, default=120, help="serving mix size")
     ap.add_argument("--profile-driver", action="store_true",

@@ -3,8 +3,11 @@
  * particle tracking (MTPT) on one AMD Instinct MI355X (gfx950).
  *
  * The method (Schauer et al., arXiv 2204.03756, Sec. 3):
- *   1. random walk X_i += xi_i sqrt(2 D_RW dt), xi_i standard normal, with
- *      zero-flux walls as elastic reflection;
+ *   1. random walk X_i += v dt + xi_i sqrt(2 D_RW dt), xi_i standard normal,
+ *      with zero-flux walls as elastic reflection (the drift v dt is the
+ *      advective term of the advection-dispersion equation, Sec. 2, which the
+ *      paper's tests leave at zero; the jump is formed in FP64 as
+ *      xi sqrt(2 D_RW dt) + v dt);
  *   2. neighbours within the search radius psi (Eq. (1));
  *   3. Gaussian weights K_ij = exp(-beta r_ij^2 / (4 D_MT dt)) (Eq. (2)-(3),
  *      the normalising prefactor cancels) and the symmetric normalisation
@@ -39,7 +42,7 @@
 extern "C" {
 #endif
 
-#define MTPT_ABI_VERSION 1
+#define MTPT_ABI_VERSION 2
 
 typedef struct mtpt_sim mtpt_sim;   /* opaque, library-owned */
 typedef struct mtpt_pool mtpt_pool; /* opaque, library-owned */
@@ -70,7 +73,7 @@ typedef struct {
     int32_t n_species;    /* 1, or 3 (A, B, C with the A+B->C reaction) */
     int32_t precision;    /* MTPT_FP64 / MTPT_FP32W_FP64ACC / MTPT_FP32_KAHAN */
     double lo[3], hi[3];  /* box [lo, hi]^dim, reflecting walls, hi > lo */
-    double d_rw;          /* random-walk diffusivity, >= 0 (0: static particles) */
+    double d_rw;          /* random-walk diffusivity, >= 0 (0 and vel = 0: static particles) */
     double d_mt;          /* mass-transfer diffusivity, > 0 */
     double dt;            /* time step, > 0 */
     double beta;          /* bandwidth/update coefficient, in (0, 1] */
@@ -78,6 +81,7 @@ typedef struct {
     double k_react;       /* A+B->C rate constant (n_species == 3), >= 0 */
     uint64_t seed;        /* Philox key of the random walk */
     int64_t start_step;   /* index of the first step (resume), >= 0 */
+    double vel[3];        /* drift velocity (advection), finite; 0 for pure dispersion */
 } mtpt_params;
 
 typedef struct {

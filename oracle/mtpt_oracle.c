@@ -25,7 +25,7 @@
  *                        cos evaluated from their series (no libm), so that any
  *                        other implementation of the same recipe can agree bit
  *                        for bit.
- *   or_rw_step           Sec. 3: random-walk update X += xi*sqrt(2 D_RW dt) and
+ *   or_rw_step           Sec. 3: random-walk update X += v dt + xi*sqrt(2 D_RW dt) and
  *                        zero-flux walls as elastic reflection.
  *   or_neighbors         Sec. 3: neighbours within the search radius psi,
  *                        Eq. (1); K-D tree range search (Bentley) or brute force.
@@ -202,12 +202,16 @@ void or_normals(uint64_t seed, int64_t step, int dim, int64_t n, double* xi /* [
 /* Sec. 3: random walk X_i(t+dt) = X_i(t) + xi_i sqrt(2 D_RW dt), then  */
 /* zero-flux walls as elastic reflection: a coordinate that left the    */
 /* box is mirrored about the wall it crossed, repeatedly until inside.  */
+/* With a drift velocity v (the advective term of the ADE, Sec. 2 and   */
+/* Sec. 8) the displacement is v dt + xi sqrt(2 D_RW dt):               */
+/* jump_k = z_k * sdev + vel_k * dt, each product and the sum rounded.  */
 /* fp32 != 0: the position state is FP32 (inputs already rounded); the  */
 /* jump is formed in FP64 and rounded once, the add and the reflection  */
 /* are done in float.                                                    */
 /* ------------------------------------------------------------------ */
 void or_rw_step(int dim, int64_t n, const double lo[3], const double hi[3], double d_rw,
-                double dt, uint64_t seed, int64_t step, int fp32, double* x /* [n][dim] */)
+                const double vel[3], double dt, uint64_t seed, int64_t step, int fp32,
+                double* x /* [n][dim] */)
 {
     double sdev = sqrt(2.0 * d_rw * dt);
 #pragma omp parallel for schedule(static)
@@ -221,7 +225,7 @@ void or_rw_step(int dim, int64_t n, const double lo[3], const double hi[3], doub
             z[2] = zz[0];
         }
         for (int k = 0; k < dim; ++k) {
-            double jump = z[k] * sdev;
+            double jump = z[k] * sdev + vel[k] * dt;
             if (fp32) {
                 float xf = (float)x[p * dim + k];
                 float jf = (float)jump;
@@ -586,8 +590,9 @@ double or_total(int64_t n, const double* v)
 
 /* ------------------------------------------------------------------ */
 /* The step loop: for each step t = start_step .. start_step+steps-1,   */
-/*   random walk (if d_rw > 0) -> neighbours within psi -> weights ->   */
-/*   mass transfer -> reaction (3 species, k_react > 0) -> record.       */
+/*   random walk (if d_rw > 0 or v != 0) -> neighbours within psi ->    */
+/*   weights -> mass transfer -> reaction (3 species, k_react > 0) ->   */
+/*   record.                                                            */
 /* fp32 != 0 keeps the position state in FP32 (the caller passes        */
 /* positions already rounded to float); the mass transfer itself is     */
 /* always FP64.  pairs_out[steps] gets the ordered pairs i != j per step */
@@ -595,9 +600,9 @@ double or_total(int64_t n, const double* v)
 /* Returns 0, or -1 on allocation failure.                              */
 /* ------------------------------------------------------------------ */
 int or_run(int dim, int64_t n, int n_species, const double* lo, const double* hi, double d_rw,
-           double d_mt, double dt, double beta, double psi, double k_react, uint64_t seed,
-           int64_t start_step, int fp32, int method, int64_t steps, double* x, double* m,
-           int64_t* pairs_out, double* totals_out, int n_threads)
+           const double* vel, double d_mt, double dt, double beta, double psi, double k_react,
+           uint64_t seed, int64_t start_step, int fp32, int method, int64_t steps, double* x,
+           double* m, int64_t* pairs_out, double* totals_out, int n_threads)
 {
 #ifdef _OPENMP
     if (n_threads > 0)
@@ -613,8 +618,11 @@ int or_run(int dim, int64_t n, int n_species, const double* lo, const double* hi
         volume = volume * (hi[k] - lo[k]);
     for (int64_t s = 0; s < steps; ++s) {
         int64_t t = start_step + s;
-        if (d_rw > 0.0)
-            or_rw_step(dim, n, lo, hi, d_rw, dt, seed, t, fp32, x);
+        int moving = d_rw > 0.0;
+        for (int k = 0; k < dim; ++k)
+            moving = moving || vel[k] != 0.0;
+        if (moving)
+            or_rw_step(dim, n, lo, hi, d_rw, vel, dt, seed, t, fp32, x);
         int64_t pairs = or_mt_step(dim, n, n_species, x, m, m2, d_mt, dt, beta, psi, method);
         if (pairs < 0) {
             free(m2);

@@ -46,7 +46,7 @@ def _load():
     lib.or_normal_pair.restype = None
     lib.or_normals.argtypes = [C.c_uint64, C.c_int64, C.c_int, C.c_int64, _f64p]
     lib.or_normals.restype = None
-    lib.or_rw_step.argtypes = [C.c_int, C.c_int64, _f64p, _f64p, C.c_double, C.c_double,
+    lib.or_rw_step.argtypes = [C.c_int, C.c_int64, _f64p, _f64p, C.c_double, _f64p, C.c_double,
                                C.c_uint64, C.c_int64, C.c_int, _f64p]
     lib.or_rw_step.restype = None
     lib.or_neighbors.argtypes = [C.c_int, C.c_int64, _f64p, C.c_double, C.c_int, _i64p, _i64p,
@@ -62,7 +62,7 @@ def _load():
     lib.or_react.restype = None
     lib.or_total.argtypes = [C.c_int64, _f64p]
     lib.or_total.restype = C.c_double
-    lib.or_run.argtypes = [C.c_int, C.c_int64, C.c_int, _f64p, _f64p, C.c_double, C.c_double,
+    lib.or_run.argtypes = [C.c_int, C.c_int64, C.c_int, _f64p, _f64p, C.c_double, _f64p, C.c_double,
                            C.c_double, C.c_double, C.c_double, C.c_double, C.c_uint64, C.c_int64,
                            C.c_int, C.c_int, C.c_int64, _f64p, _f64p, _i64p, _f64p, C.c_int]
     lib.or_run.restype = C.c_int
@@ -121,13 +121,17 @@ def normals(seed: int, step: int, dim: int, n: int) -> np.ndarray:
 
 
 # ---------------------------------------------------------- random walk ---
-def rw_step(x, lo, hi, d_rw, dt, seed, step, fp32=False) -> np.ndarray:
-    """One random-walk step with reflection; returns new positions [n][dim]."""
+def rw_step(x, lo, hi, d_rw, dt, seed, step, fp32=False, vel=None) -> np.ndarray:
+    """One random-walk step (drift vel*dt plus the jump) with reflection;
+    returns new positions [n][dim]."""
     x = _f64(x).copy()
     n, dim = x.shape
     lo3 = np.zeros(3); lo3[:dim] = lo
     hi3 = np.zeros(3); hi3[:dim] = hi
-    _load().or_rw_step(dim, n, _p(lo3, _f64p), _p(hi3, _f64p), d_rw, dt, seed, step,
+    v3 = np.zeros(3)
+    if vel is not None:
+        v3[:dim] = np.asarray(vel, dtype=np.float64)[:dim]
+    _load().or_rw_step(dim, n, _p(lo3, _f64p), _p(hi3, _f64p), d_rw, _p(v3, _f64p), dt, seed, step,
                        1 if fp32 else 0, _p(x, _f64p))
     return x
 
@@ -213,8 +217,8 @@ class RunResult:
 
 def run(params, x0, m0, steps: int, method: str = "kdtree", threads: int = 0) -> RunResult:
     """Run ``steps`` MTPT steps from (x0, m0) with ``params`` (a mapping or
-    object with dim, lo, hi, d_rw, d_mt, dt, beta, psi, k_react, seed,
-    start_step, precision).  FP32 precisions keep FP32 position state: the
+    object with dim, lo, hi, d_rw, vel (optional drift velocity), d_mt, dt,
+    beta, psi, k_react, seed, start_step, precision).  FP32 precisions keep FP32 position state: the
     inputs are rounded to float once here, as the library does at create."""
     g = params.get if isinstance(params, dict) else (lambda k, d=None: getattr(params, k, d))
     dim = int(g("dim"))
@@ -231,9 +235,14 @@ def run(params, x0, m0, steps: int, method: str = "kdtree", threads: int = 0) ->
     d_mt, dt = float(g("d_mt")), float(g("dt"))
     if psi <= 0.0:
         psi = 3.0 * math.sqrt(4.0 * d_mt * dt)
+    v3 = np.zeros(3)
+    vel = g("vel", None)
+    if vel is not None:
+        v3[:dim] = np.asarray(vel, dtype=np.float64)[:dim]
     pairs = np.zeros(steps, dtype=np.int64)
     totals = np.zeros((steps, S))
-    rc = _load().or_run(dim, n, S, _p(lo3, _f64p), _p(hi3, _f64p), float(g("d_rw", 0.0)), d_mt, dt,
+    rc = _load().or_run(dim, n, S, _p(lo3, _f64p), _p(hi3, _f64p), float(g("d_rw", 0.0)), _p(v3, _f64p),
+                        d_mt, dt,
                         float(g("beta", 0.5)), psi, float(g("k_react", 0.0) or 0.0),
                         int(g("seed", 0)), int(g("start_step", 0)), 1 if fp32 else 0,
                         {"brute": 0, "kdtree": 1}[method], steps, _p(x, _f64p), _p(m, _f64p),

@@ -92,7 +92,7 @@ struct DevStats {
 struct SimArgs {
     int64_t n;
     int32_t ns;              // species (1 or 3)
-    int32_t moving;          // random walk on (D_RW > 0)
+    int32_t moving;          // particles move (D_RW > 0 or a drift)
     // cell grid: cell side >= psi in every dimension
     double glo[3];
     double inv_side[3];
@@ -105,6 +105,7 @@ struct SimArgs {
     double lo[3], hi[3];
     float lof[3], hif[3];
     double sdev;             // sqrt(2 D_RW dt)
+    double drift[3];         // v dt, the advective displacement per step
     uint64_t seed;
     int64_t step;
     // weights: K = exp(-kc r^2), kc = beta / (4 D_MT dt)

@@ -132,43 +132,15 @@ template <int D> struct Pair<D, float> {
     }
 };
 
+// The displacement of one coordinate in the type of the positions: the FP64
+// z sdev + v dt (each operation rounded), rounded once more for FP32
+// positions; then the position after the jump, reflected at the walls.
 template <typename T>
-__device__ __forceinline__ T walk_reflect(T x, double z, double sdev, double lo, double hi,
-                                          float lof, float hif);
-
-template <>
-__device__ __forceinline__ double walk_reflect<double>(double x, double z, double sdev, double lo,
-                                                       double hi, float, float)
+__device__ __forceinline__ T jump_of(double z, double sdev, double drift)
 {
 #pragma clang fp contract(off)
-    const double jump = z * sdev;
-    double v = x + jump;
-    while (v < lo || v > hi)
-        v = (v < lo) ? 2.0 * lo - v : 2.0 * hi - v;
-    return v;
-}
-
-template <>
-__device__ __forceinline__ float walk_reflect<float>(float x, double z, double sdev, double, double,
-                                                     float lof, float hif)
-{
-#pragma clang fp contract(off)
-    const double jump = z * sdev;
-    const float jf = static_cast<float>(jump);
-    float v = x + jf;
-    while (v < lof || v > hif)
-        v = (v < lof) ? 2.0f * lof - v : 2.0f * hif - v;
-    return v;
-}
-
-// The jump of one coordinate in the type of the positions (the FP64
-// product z sdev, rounded once for FP32 positions) and the reflected
-// position; walk_reflect is the two in one.
-template <typename T>
-__device__ __forceinline__ T jump_of(double z, double sdev)
-{
-#pragma clang fp contract(off)
-    return static_cast<T>(z * sdev);
+    const double j = z * sdev + drift;
+    return static_cast<T>(j);
 }
 template <typename T>
 __device__ __forceinline__ T reflect_jump(T x, T jump, double lo, double hi, float lof, float hif);
@@ -321,7 +293,8 @@ __device__ __forceinline__ void bin_body(const SimArgs& a, uint32_t blk)
             normal_pair(a.seed, a.step, pid, 1u, &z[2], &spare);
 #pragma unroll
         for (int k = 0; k < D; ++k)
-            v[k] = walk_reflect<T>(v[k], z[k], a.sdev, a.lo[k], a.hi[k], a.lof[k], a.hif[k]);
+            v[k] = reflect_jump<T>(v[k], jump_of<T>(z[k], a.sdev, a.drift[k]), a.lo[k], a.hi[k], a.lof[k],
+                                   a.hif[k]);
     }
     uint32_t c = 0;
 #pragma unroll
@@ -520,7 +493,7 @@ __device__ __forceinline__ void place_body(const SimArgs& a, uint32_t blk)
             normal_pair(a.seed, a.step + 1, kp, 1u, &z[2], &spare);
 #pragma unroll
         for (int d = 0; d < D; ++d)
-            static_cast<T*>(a.jmp[d])[dst] = jump_of<T>(z[d], a.sdev);
+            static_cast<T*>(a.jmp[d])[dst] = jump_of<T>(z[d], a.sdev, a.drift[d]);
     }
 }
 

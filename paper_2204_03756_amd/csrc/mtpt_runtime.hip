@@ -111,6 +111,9 @@ int validate(const mtpt_params* p)
             return fail(MTPT_E_ARG, "box dimension %d: need finite lo < hi", k);
     if (!std::isfinite(p->d_rw) || p->d_rw < 0)
         return fail(MTPT_E_ARG, "d_rw must be finite and >= 0");
+    for (int k = 0; k < 3; ++k)
+        if (!std::isfinite(p->vel[k]))
+            return fail(MTPT_E_ARG, "vel must be finite");
     if (!std::isfinite(p->d_mt) || !(p->d_mt > 0))
         return fail(MTPT_E_ARG, "d_mt must be finite and > 0");
     if (!std::isfinite(p->dt) || !(p->dt > 0))
@@ -325,6 +328,8 @@ SimArgs base_args(const mtpt_sim* s)
     a.ntiles = q.ntiles;
     a.trim_rows = q.trim_rows ? 1 : 0;
     a.sdev = std::sqrt(2.0 * p.d_rw * p.dt);
+    for (int k = 0; k < 3; ++k)
+        a.drift[k] = k < q.dim ? p.vel[k] * p.dt : 0.0;
     a.seed = p.seed;
     a.psi = q.psi;
     a.psi2 = q.psi * q.psi;
@@ -615,6 +620,8 @@ int new_sim(const mtpt_params* params, const double* pos, const double* mass, vo
     s->p = *params;
     s->q = make_plan(*params);
     s->moving = params->d_rw > 0.0;
+    for (int k = 0; k < params->dim; ++k)
+        s->moving = s->moving || params->vel[k] != 0.0;
     if (alloc) {
         s->alloc.a = *alloc;
         s->alloc.custom = true;

@@ -52,6 +52,7 @@ class Params:
     seed: int = 0             # random-walk key
     start_step: int = 0
     precision: int = FP64
+    vel: List[float] = field(default_factory=lambda: [0.0, 0.0, 0.0])   # drift velocity
 
     @property
     def psi_eff(self) -> float:
@@ -70,6 +71,7 @@ class Params:
             "d_rw": self.d_rw, "d_mt": self.d_mt, "dt": self.dt, "beta": self.beta,
             "psi": self.psi, "k_react": self.k_react, "n_species": self.n_species,
             "seed": self.seed, "start_step": self.start_step, "precision": self.precision,
+            "vel": list(self.vel),
         }
 
 
@@ -145,7 +147,15 @@ def react3d(n: int = 32_000_000, steps: int = 200, precision: int = FP32W_FP64AC
     return Workload("react3d", p, x, m, steps, {"L": L})
 
 
-WORKLOADS = {"plain2d": plain2d, "rw2d": rw2d, "rw3d": rw3d, "react3d": react3d}
+def adv2d(n: int = 4_000_000, steps: int = 100, precision: int = FP32W_FP64ACC) -> Workload:
+    """rw2d with a drift velocity v = (1, 0.5) (advection-dispersion): the
+    Gaussian blob moves by v t while it spreads."""
+    w = rw2d(n=n, steps=steps, precision=precision)
+    p = replace(w.params, vel=[1.0, 0.5, 0.0], seed=0x4D54505406)
+    return Workload("adv2d", p, w.x0, w.m0, steps, {**w.notes, "vel": [1.0, 0.5]})
+
+
+WORKLOADS = {"plain2d": plain2d, "rw2d": rw2d, "rw3d": rw3d, "react3d": react3d, "adv2d": adv2d}
 
 
 def make(name: str, **kw) -> Workload:

@@ -228,6 +228,22 @@ def test_rw2d_full_size_first_steps(mt, oracle):
     say(f"  rw2d 100 steps: drift {st['drift']:.3e}, pairs/step {st['pairs_last']}")
 
 
+@pytest.mark.parametrize("dim", [2, 3])
+@pytest.mark.parametrize("prec", [W.FP64, W.FP32W_FP64ACC, W.FP32_KAHAN])
+def test_advection_parity(mt, oracle, dim, prec):
+    """Drift velocity (advection): positions bit for bit, masses at the bar.
+    In 3-d the drift pushes particles against three walls within the run."""
+    if dim == 2:
+        w = W.adv2d(n=30_000 + 17, steps=6, precision=prec)
+    else:
+        w0 = W.rw3d(n=20_000 + 5, steps=6, precision=prec, n_src=20)
+        w = W.Workload("adv3d", W.replace(w0.params, vel=[3.0, -2.0, 1.5]), w0.x0, w0.m0, 6, {})
+    check_parity(mt, oracle, w, 6)
+    # pure advection (no random walk): still re-binned every step
+    p = W.replace(w.params, d_rw=0.0)
+    check_parity(mt, oracle, W.Workload(w.name + "-pure", p, w.x0, w.m0, 6, {}), 6)
+
+
 @pytest.mark.parametrize("prec", [W.FP64, W.FP32W_FP64ACC])
 def test_sparse_grid_many_scan_tiles(mt, oracle, prec):
     """3e6 particles with a tiny psi: the grid reaches its cap of ~4 cells

@@ -275,6 +275,56 @@ def test_plain2d_spreads_as_erfc(oracle):
     assert rmse10 < 0.02
 
 
+# ----------------------------------------------------------- advection ----
+def test_drift_moves_straight_and_piles_up_at_walls(oracle):
+    """D_RW = 0 with a drift v: a particle whose straight path x0 + k v dt
+    stays inside the box is there after k steps (to the rounding of k
+    additions); one that reaches a wall is mirrored back each step and the
+    drift pushes it in again, so it stays within |v| dt of the wall it
+    drifts into (zero-flux walls hold the advected particles)."""
+    rng = np.random.default_rng(21)
+    lo, hi = np.array([0.0, 0.0]), np.array([10.0, 7.0])
+    x0 = lo + rng.random((5000, 2)) * (hi - lo)
+    vel, dt, k = np.array([1.3, -2.1]), 0.1, 20
+    p = W.Params(dim=2, n=len(x0), lo=[0.0, 0.0, 0.0], hi=[10.0, 7.0, 0.0], d_rw=0.0, d_mt=1e-4,
+                 dt=dt, vel=[vel[0], vel[1], 0.0])
+    for prec, tol in ((W.FP64, 1e-12), (W.FP32W_FP64ACC, 2e-4)):
+        p.precision = prec
+        res = oracle.run(p, x0, np.ones((1, len(x0))), k)
+        free = x0 + k * vel * dt
+        for d in range(2):
+            inside = (free[:, d] >= lo[d]) & (free[:, d] <= hi[d])
+            assert inside.sum() > 100 and (~inside).sum() > 100
+            assert np.max(np.abs(res.x[inside, d] - free[inside, d])) < tol
+            wall = hi[d] if vel[d] > 0 else lo[d]
+            gap = np.abs(res.x[~inside, d] - wall)
+            assert np.max(gap) <= abs(vel[d]) * dt * (1 + 1e-6) + tol
+    # the drift adds to the random jump: with D_RW > 0 the step is the jump of
+    # the same normals plus v dt (away from the walls)
+    xc = np.full((1000, 2), 5.0)
+    step = oracle.rw_step(xc, [-1e9, -1e9], [1e9, 1e9], 0.7, 0.1, 3, 5, vel=[1.3, -2.1])
+    free = oracle.rw_step(xc, [-1e9, -1e9], [1e9, 1e9], 0.7, 0.1, 3, 5)
+    assert np.allclose(step - free, vel * dt, atol=1e-12, rtol=0)
+
+
+def test_drift_translates_the_erfc_profile(oracle):
+    """The advection-dispersion equation: with a drift v the Heaviside
+    interface of Sec. 2.1 moves to x' + v t and spreads as before
+    (1/2 erfc((x - x' - v t)/sqrt(4 D t)) with the same effective D)."""
+    w = W.plain2d()
+    p = W.Params(**{**w.params.as_dict(), "vel": [2.0, 0.0, 0.0]})
+    t = w.steps * p.dt
+    res = oracle.run(p, w.x0, w.m0, w.steps)
+    x1 = res.x
+    d_mf = _d_eff_mean_field(1.0, p.d_mt, p.dt, p.beta, p.psi_eff, 2)
+    d_fit, rmse = _fit_erfc_d(x1, res.m[0], t, 50.0 + 2.0 * t, 15.0)
+    assert 0.5 * d_mf < d_fit < 1.05 * d_mf
+    assert rmse < 0.06
+    _, rmse_unshifted = _fit_erfc_d(x1, res.m[0], t, 50.0, 15.0)
+    assert rmse_unshifted > 3 * rmse
+    assert abs(res.totals[-1, 0] - w.m0.sum()) <= 1e-12 * w.m0.sum()
+
+
 # ------------------------------------------------------------ reaction ----
 def test_reaction_invariants_and_closed_form(oracle):
     rng = np.random.default_rng(9)
