@@ -241,6 +241,8 @@ WORKLOAD_TEXT = {
                "A+B->C mass-based reaction after each transfer, k=1",
     "adv2d": "adv2d: rw2d with a drift velocity v=(1, 0.5) (advection-dispersion), N=4e6 in "
              "[0,2000]^2, 100 steps",
+    "aniso2d": "aniso2d: rw2d with a diagonal dispersion tensor D_x=2D, D_y=D/2 (walk and mass "
+               "transfer), N=4e6 in [0,2000]^2, 100 steps",
 }
 
 
@@ -251,7 +253,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
-    ap.add_argument("--workload", default="rw2d", choices=["rw2d", "rw3d", "react3d", "adv2d", "serve"],
+    ap.add_argument("--workload", default="rw2d", choices=["rw2d", "rw3d", "react3d", "adv2d", "aniso2d", "serve"],
                     help="rw2d is the benchmark line; the others are reported the same way")
     ap.add_argument("--requests", type=int, default=120, help="serving mix size")
     ap.add_argument("--profile-driver", action="store_true",

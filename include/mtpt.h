@@ -42,7 +42,7 @@
 extern "C" {
 #endif
 
-#define MTPT_ABI_VERSION 2
+#define MTPT_ABI_VERSION 3
 
 typedef struct mtpt_sim mtpt_sim;   /* opaque, library-owned */
 typedef struct mtpt_pool mtpt_pool; /* opaque, library-owned */
@@ -82,7 +82,20 @@ typedef struct {
     uint64_t seed;        /* Philox key of the random walk */
     int64_t start_step;   /* index of the first step (resume), >= 0 */
     double vel[3];        /* drift velocity (advection), finite; 0 for pure dispersion */
+    double aniso[3];      /* anisotropic dispersion: D_RW and D_MT along axis k are
+                             aniso[k] times d_rw and d_mt (all > 0), or all 0 for
+                             isotropic dispersion; see the note below */
 } mtpt_params;
+
+/* Anisotropic dispersion (a diagonal dispersion tensor in the kernel of
+ * Sec. 3): the walk and the mass transfer share the tensor diag(aniso),
+ * scaled by d_rw and d_mt respectively.  The step is then isotropic in the
+ * frame x'_k = x_k c_k with c_k = 1/sqrt(aniso_k), where the library runs it:
+ * box and vel are scaled alike, positions are multiplied by c_k in FP64 at
+ * create (then rounded once to the position type) and divided by c_k in
+ * FP64 by mtpt_positions.  psi and the neighbour sets of mtpt_neighbors are
+ * those of the scaled frame; in the caller's frame the cutoff is the
+ * ellipsoid sum_k dx_k^2 / aniso_k <= psi^2. */
 
 typedef struct {
     void* (*alloc)(size_t bytes, void* ctx); /* returns device memory or NULL */

@@ -217,8 +217,9 @@ class RunResult:
 
 def run(params, x0, m0, steps: int, method: str = "kdtree", threads: int = 0) -> RunResult:
     """Run ``steps`` MTPT steps from (x0, m0) with ``params`` (a mapping or
-    object with dim, lo, hi, d_rw, vel (optional drift velocity), d_mt, dt,
-    beta, psi, k_react, seed, start_step, precision).  FP32 precisions keep FP32 position state: the
+    object with dim, lo, hi, d_rw, vel (optional drift velocity), aniso
+    (optional per-axis dispersion factors), d_mt, dt, beta, psi, k_react, seed,
+    start_step, precision).  FP32 precisions keep FP32 position state: the
     inputs are rounded to float once here, as the library does at create."""
     g = params.get if isinstance(params, dict) else (lambda k, d=None: getattr(params, k, d))
     dim = int(g("dim"))
@@ -226,11 +227,19 @@ def run(params, x0, m0, steps: int, method: str = "kdtree", threads: int = 0) ->
     n = x.shape[0]
     m = _f64(np.atleast_2d(m0)).copy()
     S = m.shape[0]
+    # anisotropic dispersion D_k = aniso_k D: the isotropic step in the frame
+    # x'_k = x_k c_k, c_k = 1/sqrt(aniso_k) (positions, box and drift scaled
+    # in FP64; positions rounded to float afterwards in the FP32 modes)
+    sc = np.ones(dim)
+    aniso = g("aniso", None)
+    if aniso is not None and any(float(a) > 0.0 for a in list(aniso)[:dim]):
+        sc = 1.0 / np.sqrt(np.asarray(aniso, dtype=np.float64)[:dim])
+    x = x * sc
     fp32 = int(g("precision", 0)) != 0
     if fp32:
         x = x.astype(np.float32).astype(np.float64)
-    lo3 = np.zeros(3); lo3[:dim] = g("lo")[:dim]
-    hi3 = np.zeros(3); hi3[:dim] = g("hi")[:dim]
+    lo3 = np.zeros(3); lo3[:dim] = np.asarray(g("lo")[:dim], dtype=np.float64) * sc
+    hi3 = np.zeros(3); hi3[:dim] = np.asarray(g("hi")[:dim], dtype=np.float64) * sc
     psi = float(g("psi", 0.0) or 0.0)
     d_mt, dt = float(g("d_mt")), float(g("dt"))
     if psi <= 0.0:
@@ -238,7 +247,7 @@ def run(params, x0, m0, steps: int, method: str = "kdtree", threads: int = 0) ->
     v3 = np.zeros(3)
     vel = g("vel", None)
     if vel is not None:
-        v3[:dim] = np.asarray(vel, dtype=np.float64)[:dim]
+        v3[:dim] = np.asarray(vel, dtype=np.float64)[:dim] * sc
     pairs = np.zeros(steps, dtype=np.int64)
     totals = np.zeros((steps, S))
     rc = _load().or_run(dim, n, S, _p(lo3, _f64p), _p(hi3, _f64p), float(g("d_rw", 0.0)), _p(v3, _f64p),
@@ -249,4 +258,4 @@ def run(params, x0, m0, steps: int, method: str = "kdtree", threads: int = 0) ->
                         _p(pairs, _i64p), _p(totals, _f64p), int(threads))
     if rc != 0:
         raise MemoryError("oracle run")
-    return RunResult(x=x, m=m, pairs=pairs, totals=totals)
+    return RunResult(x=x / sc, m=m, pairs=pairs, totals=totals)

@@ -114,6 +114,16 @@ int validate(const mtpt_params* p)
     for (int k = 0; k < 3; ++k)
         if (!std::isfinite(p->vel[k]))
             return fail(MTPT_E_ARG, "vel must be finite");
+    {
+        int zero = 0;
+        for (int k = 0; k < p->dim; ++k) {
+            if (!std::isfinite(p->aniso[k]) || p->aniso[k] < 0)
+                return fail(MTPT_E_ARG, "aniso must be finite and >= 0");
+            zero += p->aniso[k] == 0.0;
+        }
+        if (zero != 0 && zero != p->dim)
+            return fail(MTPT_E_ARG, "aniso: all components > 0, or all 0 (isotropic)");
+    }
     if (!std::isfinite(p->d_mt) || !(p->d_mt > 0))
         return fail(MTPT_E_ARG, "d_mt must be finite and > 0");
     if (!std::isfinite(p->dt) || !(p->dt > 0))
@@ -240,7 +250,8 @@ struct PhaseEv {
 }  // namespace
 
 struct mtpt_sim {
-    mtpt_params p{};
+    mtpt_params p{};          // the parameters in the scaled frame (box, drift)
+    double scale[3] = {1.0, 1.0, 1.0};   // x' = x scale_k (anisotropic dispersion)
     Plan q;
     Alloc alloc;
     hipStream_t stream = nullptr;
@@ -534,14 +545,17 @@ int create_into(mtpt_sim* s, const double* pos, const double* mass)
     if (n > 0) {
         std::vector<unsigned char> stage(std::max(n * q.tsz, n * q.msz));
         for (int k = 0; k < q.dim; ++k) {
+            // the scaled frame x' = x scale_k in FP64, rounded once to the
+            // position type
+            const double sc = s->scale[k];
             if (q.tsz == 8) {
                 double* d = reinterpret_cast<double*>(stage.data());
                 for (size_t i = 0; i < n; ++i)
-                    d[i] = pos[i * q.dim + k];
+                    d[i] = pos[i * q.dim + k] * sc;
             } else {
                 float* f = reinterpret_cast<float*>(stage.data());
                 for (size_t i = 0; i < n; ++i)
-                    f[i] = static_cast<float>(pos[i * q.dim + k]);
+                    f[i] = static_cast<float>(pos[i * q.dim + k] * sc);
             }
             HIP_TRY(hipMemcpy(s->X[k], stage.data(), n * q.tsz, hipMemcpyHostToDevice));
         }
@@ -617,11 +631,20 @@ int new_sim(const mtpt_params* params, const double* pos, const double* mass, vo
     if (alloc && (!alloc->alloc || !alloc->free))
         return fail(MTPT_E_ARG, "allocator needs both alloc and free");
     mtpt_sim* s = new mtpt_sim();
+    // anisotropic dispersion D_k = aniso_k D: the step is isotropic in the
+    // frame x'_k = x_k / sqrt(aniso_k), where box and drift are scaled too
     s->p = *params;
-    s->q = make_plan(*params);
-    s->moving = params->d_rw > 0.0;
+    for (int k = 0; k < params->dim; ++k) {
+        if (params->aniso[k] > 0.0)
+            s->scale[k] = 1.0 / std::sqrt(params->aniso[k]);
+        s->p.lo[k] = params->lo[k] * s->scale[k];
+        s->p.hi[k] = params->hi[k] * s->scale[k];
+        s->p.vel[k] = params->vel[k] * s->scale[k];
+    }
+    s->q = make_plan(s->p);
+    s->moving = s->p.d_rw > 0.0;
     for (int k = 0; k < params->dim; ++k)
-        s->moving = s->moving || params->vel[k] != 0.0;
+        s->moving = s->moving || s->p.vel[k] != 0.0;
     if (alloc) {
         s->alloc.a = *alloc;
         s->alloc.custom = true;
@@ -747,6 +770,12 @@ int mtpt_positions(mtpt_sim* s, double* out)
     s->alloc.put(d);
     if (e != hipSuccess)
         return fail(MTPT_E_DEVICE, "mtpt_positions: %s", hipGetErrorString(e));
+    // back from the scaled frame: x = x' / scale_k (FP64)
+    const int dim = s->q.dim;
+    for (int k = 0; k < dim; ++k)
+        if (s->scale[k] != 1.0)
+            for (size_t i = 0; i < n; ++i)
+                out[i * dim + k] = out[i * dim + k] / s->scale[k];
     return MTPT_OK;
 }
 

@@ -17,7 +17,7 @@ import numpy as np
 
 from . import build as _build
 
-MTPT_ABI_VERSION = 2
+MTPT_ABI_VERSION = 3
 MTPT_OK, MTPT_E_ARG, MTPT_E_NOMEM, MTPT_E_DEVICE, MTPT_E_NONFINITE, MTPT_E_ABI, MTPT_E_STATE = \
     0, -1, -2, -3, -4, -5, -6
 MTPT_FP64, MTPT_FP32W_FP64ACC, MTPT_FP32_KAHAN = 0, 1, 2
@@ -37,7 +37,7 @@ class mtpt_params(C.Structure):
         ("d_rw", C.c_double), ("d_mt", C.c_double), ("dt", C.c_double), ("beta", C.c_double),
         ("psi", C.c_double), ("k_react", C.c_double),
         ("seed", C.c_uint64), ("start_step", C.c_int64),
-        ("vel", C.c_double * 3),
+        ("vel", C.c_double * 3), ("aniso", C.c_double * 3),
     ]
 
 
@@ -140,6 +140,9 @@ def make_params(p) -> mtpt_params:
     vel = getattr(p, "vel", None) or (0.0, 0.0, 0.0)
     for k in range(3):
         q.vel[k] = float(vel[k]) if k < len(vel) else 0.0
+    aniso = getattr(p, "aniso", None) or (0.0, 0.0, 0.0)
+    for k in range(3):
+        q.aniso[k] = float(aniso[k]) if k < len(aniso) else 0.0
     return q
 
 

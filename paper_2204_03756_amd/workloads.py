@@ -53,6 +53,7 @@ class Params:
     start_step: int = 0
     precision: int = FP64
     vel: List[float] = field(default_factory=lambda: [0.0, 0.0, 0.0])   # drift velocity
+    aniso: List[float] = field(default_factory=lambda: [0.0, 0.0, 0.0])  # D_k / D (0: isotropic)
 
     @property
     def psi_eff(self) -> float:
@@ -71,7 +72,7 @@ class Params:
             "d_rw": self.d_rw, "d_mt": self.d_mt, "dt": self.dt, "beta": self.beta,
             "psi": self.psi, "k_react": self.k_react, "n_species": self.n_species,
             "seed": self.seed, "start_step": self.start_step, "precision": self.precision,
-            "vel": list(self.vel),
+            "vel": list(self.vel), "aniso": list(self.aniso),
         }
 
 
@@ -155,7 +156,16 @@ def adv2d(n: int = 4_000_000, steps: int = 100, precision: int = FP32W_FP64ACC) 
     return Workload("adv2d", p, w.x0, w.m0, steps, {**w.notes, "vel": [1.0, 0.5]})
 
 
-WORKLOADS = {"plain2d": plain2d, "rw2d": rw2d, "rw3d": rw3d, "react3d": react3d, "adv2d": adv2d}
+def aniso2d(n: int = 4_000_000, steps: int = 100, precision: int = FP32W_FP64ACC) -> Workload:
+    """rw2d with a diagonal dispersion tensor D_x = 2 D, D_y = D / 2 (the walk
+    and the mass transfer alike): the blob spreads into an ellipse."""
+    w = rw2d(n=n, steps=steps, precision=precision)
+    p = replace(w.params, aniso=[2.0, 0.5, 0.0], seed=0x4D54505407)
+    return Workload("aniso2d", p, w.x0, w.m0, steps, {**w.notes, "aniso": [2.0, 0.5]})
+
+
+WORKLOADS = {"plain2d": plain2d, "rw2d": rw2d, "rw3d": rw3d, "react3d": react3d, "adv2d": adv2d,
+             "aniso2d": aniso2d}
 
 
 def make(name: str, **kw) -> Workload:

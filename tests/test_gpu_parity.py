@@ -244,6 +244,21 @@ def test_advection_parity(mt, oracle, dim, prec):
     check_parity(mt, oracle, W.Workload(w.name + "-pure", p, w.x0, w.m0, 6, {}), 6)
 
 
+@pytest.mark.parametrize("dim", [2, 3])
+@pytest.mark.parametrize("prec", [W.FP64, W.FP32W_FP64ACC, W.FP32_KAHAN])
+def test_anisotropic_parity(mt, oracle, dim, prec):
+    """Diagonal dispersion tensor (the isotropic step in the scaled frame):
+    positions bit for bit in the caller's frame, masses at the bar; in 3-d
+    with a drift as well."""
+    if dim == 2:
+        w = W.aniso2d(n=30_000 + 29, steps=6, precision=prec)
+    else:
+        w0 = W.rw3d(n=20_000 + 7, steps=6, precision=prec, n_src=20)
+        p = W.replace(w0.params, aniso=[1.5, 0.8, 0.5], vel=[1.0, 0.0, -2.0])
+        w = W.Workload("aniso3d", p, w0.x0, w0.m0, 6, {})
+    check_parity(mt, oracle, w, 6)
+
+
 @pytest.mark.parametrize("prec", [W.FP64, W.FP32W_FP64ACC])
 def test_sparse_grid_many_scan_tiles(mt, oracle, prec):
     """3e6 particles with a tiny psi: the grid reaches its cap of ~4 cells

@@ -325,6 +325,65 @@ def test_drift_translates_the_erfc_profile(oracle):
     assert abs(res.totals[-1, 0] - w.m0.sum()) <= 1e-12 * w.m0.sum()
 
 
+# ----------------------------------------------- anisotropic dispersion ----
+def test_anisotropic_pair_closed_form(oracle):
+    """A diagonal dispersion tensor D_k = a_k D: a pair at distance r along
+    axis k exchanges with K = exp(-beta r^2 / (4 a_k D_MT dt)), and the cutoff
+    is the ellipsoid sum_k dx_k^2 / a_k <= psi^2."""
+    d_mt, dt, beta, r = 0.7, 0.1, 0.5, 0.9
+    a = [4.0, 0.25]
+    m = np.array([[0.3, 1.7]])
+    for axis in (0, 1):
+        x = np.array([[10.0, 10.0], [10.0, 10.0]])
+        x[1, axis] += r
+        p = W.Params(dim=2, n=2, lo=[0.0, 0.0, 0.0], hi=[20.0, 20.0, 0.0], d_rw=0.0, d_mt=d_mt,
+                     dt=dt, beta=beta, psi=2.0, aniso=[a[0], a[1], 0.0])
+        res = oracle.run(p, x, m, 1, method="brute")
+        K = math.exp(-beta * r * r / (4 * a[axis] * d_mt * dt))
+        expect = 0.3 + beta * K / (1 + K) * (1.7 - 0.3)
+        if r * r / a[axis] <= 2.0 ** 2:
+            assert res.pairs[0] == 2
+            assert res.m[0, 0] == pytest.approx(expect, rel=1e-14)
+            assert res.m[0, 1] == pytest.approx(2.0 - expect, rel=1e-14)
+        else:
+            assert res.pairs[0] == 0 and np.array_equal(res.m, m)
+        assert np.array_equal(res.x, x)
+    # along y the ellipse is 4x narrower: a pair at 0.9 in y (0.9^2/0.25 = 3.24)
+    # interacts with psi = 2, one at 1.1 (4.84 > 4) does not
+    x = np.array([[10.0, 10.0], [10.0, 11.1]])
+    p = W.Params(dim=2, n=2, lo=[0.0, 0.0, 0.0], hi=[20.0, 20.0, 0.0], d_rw=0.0, d_mt=d_mt,
+                 dt=dt, beta=beta, psi=2.0, aniso=[a[0], a[1], 0.0])
+    assert oracle.run(p, x, m, 1, method="brute").pairs[0] == 0
+
+
+def test_anisotropic_spreading_rates(oracle):
+    """Heaviside fronts across x and across y spread with D_x / D_y = a_x / a_y
+    (the erfc fit of Sec. 2.1 along each axis): at density 10 each fitted D
+    is a_k times the mean-field effective D of the isotropic frame, within the
+    bounds the isotropic test uses (a_x a_y = 1 keeps the frame's density)."""
+    n = 40_000
+    L = math.sqrt(n / 10.0)
+    w = W.plain2d(n=n)
+    x0 = w.x0 * (L / w.params.hi[0])
+    ax, ay = 2.0, 0.5
+    p = W.Params(**{**w.params.as_dict(), "hi": [L, L, 0.0], "aniso": [ax, ay, 0.0]})
+    t = 50 * p.dt
+    d_mf = _d_eff_mean_field(10.0, p.d_mt, p.dt, p.beta, p.psi_eff, 2)
+    fits = []
+    for axis, a in ((0, ax), (1, ay)):
+        m0 = (x0[:, axis] < L / 2).astype(np.float64)[None, :]
+        res = oracle.run(p, x0, m0, 50)
+        xs = x0[:, [axis, 1 - axis]]
+        Ds = np.linspace(0.05, 3.0, 1181)
+        mask = np.abs(xs[:, 0] - L / 2) < 15.0
+        err = [np.mean((res.m[0][mask] - 0.5 * special.erfc((xs[mask, 0] - L / 2) /
+                                                             math.sqrt(4 * D * t))) ** 2) for D in Ds]
+        d_fit = Ds[int(np.argmin(err))]
+        assert 0.90 * a * d_mf < d_fit <= 1.02 * a * d_mf
+        fits.append(d_fit)
+    assert fits[0] / fits[1] == pytest.approx(ax / ay, rel=0.1)
+
+
 # ------------------------------------------------------------ reaction ----
 def test_reaction_invariants_and_closed_form(oracle):
     rng = np.random.default_rng(9)
