@@ -73,6 +73,9 @@ def test_validation_rejects_bad_params(lib):
     p = mtpt.make_params(w.params); p.beta = 1.5; cases.append((p, mtpt.MTPT_E_ARG))
     p = mtpt.make_params(w.params); p.hi[1] = p.lo[1]; cases.append((p, mtpt.MTPT_E_ARG))
     p = mtpt.make_params(w.params); p.start_step = -3; cases.append((p, mtpt.MTPT_E_ARG))
+    p = mtpt.make_params(w.params); p.vel[0] = float("inf"); cases.append((p, mtpt.MTPT_E_ARG))
+    p = mtpt.make_params(w.params); p.aniso[0] = 2.0; cases.append((p, mtpt.MTPT_E_ARG))
+    p = mtpt.make_params(w.params); p.aniso[0] = -1.0; p.aniso[1] = 1.0; cases.append((p, mtpt.MTPT_E_ARG))
     for p, code in cases:
         rc, h = _call_create(lib, p, x, m)
         assert rc == code and not h.value
