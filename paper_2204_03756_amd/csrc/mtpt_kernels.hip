@@ -109,9 +109,10 @@ template <int D> struct Pair<D, float> {
     {
         const float r2 = Pair::r2(xi, xj);
         *r2o = r2;
-        bool in = r2 < a.psi2_in;
-        const bool band = (r2 <= a.psi2_out) && !in;
-        if (__builtin_expect(band, 0)) {
+        // below psi2_in inside for sure, above psi2_out outside; between the
+        // two the FP64 test decides
+        bool in = r2 <= a.psi2_out;
+        if (__builtin_expect(in && r2 >= a.psi2_in, 0)) {
             double pi[3], pj[3];
 #pragma unroll
             for (int k = 0; k < D; ++k) {
@@ -446,12 +447,18 @@ __device__ __forceinline__ void place_body(const SimArgs& a, uint32_t blk)
     const T* xt0 = static_cast<const T*>(a.xt[0]);
     uint32_t src = 0, kp = 0, c = 0;
     T xv[3];
+    M mv[3];
     if (live) {
         src = a.perm[k];
 #pragma unroll
         for (int d = 0; d < D; ++d)
             xv[d] = static_cast<const T*>(a.xt[d])[src];
         kp = a.pid_src[src];
+        // the masses are gathered with the keys, not after the ranking
+#pragma unroll
+        for (int s = 0; s < 3; ++s)
+            if (s < a.ns)
+                mv[s] = static_cast<const M*>(a.m_src[s])[src];
         c = cell_index<D, T>(a, xv);
         lkx[threadIdx.x] = xv[0];
         lkp[threadIdx.x] = kp;
@@ -481,8 +488,10 @@ __device__ __forceinline__ void place_body(const SimArgs& a, uint32_t blk)
 #pragma unroll
     for (int d = 0; d < D; ++d)
         static_cast<T*>(a.x[d])[dst] = xv[d];
-    for (int s = 0; s < a.ns; ++s)
-        static_cast<M*>(a.m_mid[s])[dst] = static_cast<const M*>(a.m_src[s])[src];
+#pragma unroll
+    for (int s = 0; s < 3; ++s)
+        if (s < a.ns)
+            static_cast<M*>(a.m_mid[s])[dst] = mv[s];
     a.pid_dst[dst] = kp;
     if (a.fuse_bin) {
         // the jumps of the step after a.step, for the transfer pass's walk
@@ -593,7 +602,7 @@ __device__ __forceinline__ void scan_row(const SimArgs& a, PX p, PS sr, PM ms, u
                     acc.comp[c] = (t - acc.dl[c]) - y;
                     acc.dl[c] = t;
                 } else {
-                    acc.dl[c] += static_cast<A>(w) * static_cast<A>(mj - acc.mi[c]);
+                    acc.dl[c] = __builtin_fma(static_cast<A>(w), static_cast<A>(mj - acc.mi[c]), acc.dl[c]);
                 }
             }
         }
@@ -945,24 +954,40 @@ __device__ __forceinline__ void tile_body(const SimArgs& a, uint32_t blk)
                     b2 = bb[2]; l2 = ll[2];
                 }
                 const uint32_t tot = act ? l0 + l1 + l2 : 0u;
-                const uint32_t o1 = b1 - l0, o2 = b2 - l0 - l1;
+                // LDS byte offset of candidate k of the concatenated rows: k
+                // sizeof(T) plus its row's offset (kept opaque so that the
+                // scaling is not folded back into the candidate loops); a
+                // candidate past the lane's rows reads the particle's own slot
+                constexpr uint32_t kT = static_cast<uint32_t>(sizeof(T));
+                uint32_t ob0 = b0 * kT, ob1 = (b1 - l0) * kT, ob2 = (b2 - l0 - l1) * kT, obs = li * kT;
+                asm volatile("" : "+v"(ob0), "+v"(ob1), "+v"(ob2), "+v"(obs));
+                const uint32_t e0 = l0, e1 = l0 + l1;
+                auto slot_of = [ob0, ob1, ob2, obs, e0, e1](uint32_t k, bool valid) {
+                    const uint32_t off = k * kT + (k < e0 ? ob0 : (k < e1 ? ob1 : ob2));
+                    return valid ? off : obs;
+                };
+                auto ld = [](const auto* base, uint32_t off) {
+                    return *reinterpret_cast<const std::remove_cv_t<std::remove_reference_t<decltype(*base)>>*>(
+                        reinterpret_cast<const char*>(base) + off);
+                };
                 uint32_t kmax = tot;
 #pragma unroll
                 for (int off = 32; off >= 1; off >>= 1)
                     kmax = max(kmax, static_cast<uint32_t>(__shfl_xor(static_cast<int>(kmax), off, 64)));
                 kmax = __builtin_amdgcn_readfirstlane(kmax);
                 constexpr int kUnroll = D == 3 ? MTPT_CAND_UNROLL_3D : MTPT_CAND_UNROLL_2D;
-                // one candidate: LDS slot idx, pair counted when in
-                auto visit = [&](uint32_t idx, bool in, T r2) {
+                // one candidate at LDS byte offset off (of the T arrays), pair
+                // counted when in
+                auto visit = [&](uint32_t off, bool in, T r2) {
                     const T kv = Pair<D, T>::kernel(a, r2);
                     if constexpr (!TRANSFER) {
                         acc.s += in ? kv : T(0);
                     } else {
                         using A = typename Types<PREC>::A;
-                        const T w = Pair<D, T>::weight(kv, acc.si, lsr[idx]);
+                        const T w = Pair<D, T>::weight(kv, acc.si, ld(lsr, off));
 #pragma unroll
                         for (int c = 0; c < NS; ++c) {
-                            const M mj = lms[c][idx];
+                            const M mj = ld(lms[c], off * static_cast<uint32_t>(sizeof(M) / sizeof(T)));
                             if (PREC == 2) {
                                 const A y = static_cast<A>(w) * static_cast<A>(mj - acc.mi[c]) - acc.comp[c];
                                 const A tk = acc.dl[c] + y;
@@ -970,8 +995,10 @@ __device__ __forceinline__ void tile_body(const SimArgs& a, uint32_t blk)
                                 acc.comp[c] = in ? cn : acc.comp[c];
                                 acc.dl[c] = in ? tk : acc.dl[c];
                             } else {
-                                const A d = static_cast<A>(w) * static_cast<A>(mj - acc.mi[c]);
-                                acc.dl[c] += in ? d : A(0);
+                                // one rounding per increment, in the mask loop
+                                // and the full loop alike
+                                const A dm = static_cast<A>(mj - acc.mi[c]);
+                                acc.dl[c] = __builtin_fma(static_cast<A>(w), in ? dm : A(0), acc.dl[c]);
                             }
                         }
                     }
@@ -991,40 +1018,44 @@ __device__ __forceinline__ void tile_body(const SimArgs& a, uint32_t blk)
                         const bool valid = mk != 0ull;
                         const uint32_t k = valid ? static_cast<uint32_t>(__builtin_ctzll(mk)) : 0u;
                         mk &= mk - 1ull;
-                        uint32_t idx = k + (k < l0 ? b0 : (k < l0 + l1 ? o1 : o2));
-                        idx = valid ? idx : li;
+                        const uint32_t off = slot_of(k, valid);
                         T xj[3];
 #pragma unroll
                         for (int d = 0; d < D; ++d)
-                            xj[d] = lpos[d][idx];
-                        visit(idx, valid, Pair<D, T>::r2(xi, xj));
+                            xj[d] = ld(lpos[d], off);
+                        // a lane without a neighbour left visits its own slot:
+                        // r^2 = 0 and m_j - m_i = 0 give an increment of exactly
+                        // zero, which only the compensated sum has to skip
+                        visit(off, PREC == 2 ? valid : true, Pair<D, T>::r2(xi, xj));
                     }
                     continue;
                 }
                 uint32_t mlo = 0, mhi = 0;
                 // candidates in chunks of 32 (the chunk's mask word is
-                // built without a branch)
+                // built without a branch: shifted in, first candidate
+                // highest, then bit-reversed)
                 for (uint32_t k0 = 0; k0 < kmax; k0 += 32u) {
                     const uint32_t kend = min(kmax, k0 + 32u);
                     uint32_t mw = 0;
 #pragma unroll kUnroll
                     for (uint32_t k = k0; k < kend; ++k) {
                         const bool valid = k < tot;
-                        uint32_t idx = k + (k < l0 ? b0 : (k < l0 + l1 ? o1 : o2));
-                        idx = valid ? idx : li;
+                        const uint32_t off = slot_of(k, valid);
                         T xj[3];
 #pragma unroll
                         for (int d = 0; d < D; ++d)
-                            xj[d] = lpos[d][idx];
+                            xj[d] = ld(lpos[d], off);
                         T r2;
                         bool in = Pair<D, T>::inside(a, xi, xj, &r2) && valid;
                         if (TRANSFER)
-                            in = in && idx != li;
-                        visit(idx, in, r2);
+                            in = in && off != obs;
+                        visit(off, in, r2);
                         if constexpr (!TRANSFER)
-                            mw |= in ? (1u << (k - k0)) : 0u;
+                            mw = (mw << 1) | (in ? 1u : 0u);
                     }
                     if constexpr (!TRANSFER) {
+                        // candidate k0 + j at bit j
+                        mw = __builtin_bitreverse32(mw) >> (32u - (kend - k0));
                         // the particle itself is candidate l0 + (li - b1) of
                         // its own plane's middle row
                         if (pzr == planes / 2) {
