@@ -206,17 +206,43 @@ template <> struct Window<float> {
     }
 };
 
-// wave64 inclusive scan and workgroup exclusive scan (kBlock threads)
+// Wave64 primitives on DPP lane moves (no LDS round trip).  Every lane of
+// the wave must be active.
+// one DPP move: lane value from the lane that dpp_ctrl selects, 0 where that
+// lane is outside the row or the row is masked off
+template <int Ctrl, int RowMask = 0xF>
+__device__ __forceinline__ uint32_t dpp_u32(uint32_t v)
+{
+    return static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(v), Ctrl, RowMask, 0xF, true));
+}
+
+// inclusive scan over the 64 lanes: shifts by 1, 2, 4 and 8 inside each row
+// of 16 lanes, then the last lane of row 0 (2) added to row 1 (3) and the
+// last lane of row 1 added to rows 2 and 3
 __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v)
 {
-    const int lane = threadIdx.x & 63;
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        const uint32_t t = __shfl_up(v, off, 64);
-        if (lane >= off)
-            v += t;
-    }
+    v += dpp_u32<0x111>(v);          // row_shr:1
+    v += dpp_u32<0x112>(v);          // row_shr:2
+    v += dpp_u32<0x114>(v);          // row_shr:4
+    v += dpp_u32<0x118>(v);          // row_shr:8
+    v += dpp_u32<0x142, 0xA>(v);     // row_bcast:15 into rows 1 and 3
+    v += dpp_u32<0x143, 0xC>(v);     // row_bcast:31 into rows 2 and 3
     return v;
+}
+
+// maximum over the 64 lanes, wave-uniform: the maximum of every quad, then of
+// every row (rotations by 4 and 8), then of the four rows' lanes 0
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v)
+{
+    v = max(v, dpp_u32<0xB1>(v));    // quad_perm [1,0,3,2]
+    v = max(v, dpp_u32<0x4E>(v));    // quad_perm [2,3,0,1]
+    v = max(v, dpp_u32<0x124>(v));   // row_ror:4
+    v = max(v, dpp_u32<0x128>(v));   // row_ror:8
+    const uint32_t r0 = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(v), 0));
+    const uint32_t r1 = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(v), 16));
+    const uint32_t r2 = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(v), 32));
+    const uint32_t r3 = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(v), 48));
+    return max(max(r0, r1), max(r2, r3));
 }
 
 __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* total)
@@ -657,8 +683,8 @@ __device__ __forceinline__ void tile_body(const SimArgs& a, uint32_t blk)
     __shared__ uint32_t cst[kSegs][TileLimits<D>::cols];
     __shared__ uint32_t own_gb[kRows];
     __shared__ uint32_t own_pre[kRows + 1];
-    // the row table and row-wise staging, except in the 3-d three-species
-    // transfer pass (their registers would cost it a wave per SIMD)
+    // the own-row table, except in the 3-d three-species transfer pass (its
+    // registers would cost that pass a wave per SIMD)
     constexpr bool kLean = !(D == 3 && NS == 3 && TRANSFER);
     __shared__ uint8_t row_of[kLean ? CAP : 1];   // own row of each own particle
     // 2-d FP64 row-sum pass: own cells in order of their candidate count, so
@@ -695,17 +721,25 @@ __device__ __forceinline__ void tile_body(const SimArgs& a, uint32_t blk)
         for (int k = tid; k < tw * nrow; k += kBlock)
             hist[k] = 0u;
 
+    // every cell boundary of the halo rows in one round of loads, as global
+    // slots (a row outside the grid is empty); the runs of the halo rows and
+    // of the own rows follow from it
+    const int ncb = ncol + 1;
+    for (int idx = tid; idx < nseg * ncb; idx += kBlock) {
+        const int sg = idx / ncb;
+        const int c = idx - sg * ncb;
+        const int pz = D == 3 ? tz - 1 + sg / rows : 0;
+        const int py = y0 - 1 + sg % rows;
+        uint32_t v = 0;
+        if (py >= 0 && py < nc1 && pz >= 0 && pz < nc2)
+            v = a.starts[(static_cast<uint32_t>(pz) * nc1 + py) * nc0 + xa + c];
+        cst[sg][c] = v;
+    }
+    __syncthreads();
     uint32_t slen = 0;
     if (tid < nseg) {
-        const int pz = D == 3 ? tz - 1 + tid / rows : 0;
-        const int py = y0 - 1 + tid % rows;
-        uint32_t gb = 0;
-        if (py >= 0 && py < nc1 && pz >= 0 && pz < nc2) {
-            const uint32_t rb = (static_cast<uint32_t>(pz) * nc1 + py) * nc0;
-            gb = a.starts[rb + xa];
-            slen = a.starts[rb + xb] - gb;
-        }
-        seg_gb[tid] = gb;
+        seg_gb[tid] = cst[tid][0];
+        slen = cst[tid][ncol] - cst[tid][0];
     }
     uint32_t total;
     const uint32_t soff = block_excl_scan(slen, &total);
@@ -713,11 +747,12 @@ __device__ __forceinline__ void tile_body(const SimArgs& a, uint32_t blk)
         seg_off[tid] = soff;
     if (tid == 0)
         seg_off[nseg] = total;
+    // own row r is halo row r + 1 of the middle plane
+    const int smid = (planes / 2) * rows + 1;
     uint32_t olen = 0;
     if (tid < nrow) {
-        const uint32_t rb = (static_cast<uint32_t>(D == 3 ? tz : 0) * nc1 + (y0 + tid)) * nc0;
-        const uint32_t gb = a.starts[rb + x0];
-        olen = a.starts[rb + x1] - gb;
+        const uint32_t gb = cst[smid + tid][x0 - xa];
+        olen = cst[smid + tid][x1 - xa] - gb;
         own_gb[tid] = gb;
     }
     uint32_t own_total;
@@ -732,21 +767,14 @@ __device__ __forceinline__ void tile_body(const SimArgs& a, uint32_t blk)
     // the row-sum pass (one-species instantiation) staged this tile in LDS
     // too, so it recorded the neighbour masks
     const bool mask_ok = total <= static_cast<uint32_t>(TileCap<D, PREC, 1, false>::value);
-    // cell boundaries of every halo row, as LDS offsets (or global slots)
-    for (int idx = tid; idx < nseg * (ncol + 1); idx += kBlock) {
-        const int sg = idx / (ncol + 1);
-        const int c = idx - sg * (ncol + 1);
-        const int pz = D == 3 ? tz - 1 + sg / rows : 0;
-        const int py = y0 - 1 + sg % rows;
-        uint32_t v = use_lds ? seg_off[sg] : seg_gb[sg];
-        if (py >= 0 && py < nc1 && pz >= 0 && pz < nc2) {
-            const uint32_t rb = (static_cast<uint32_t>(pz) * nc1 + py) * nc0;
-            v = a.starts[rb + xa + c];
-            if (use_lds)
-                v = v - seg_gb[sg] + seg_off[sg];
+    // cell boundaries of every halo row as LDS offsets (kept as global slots
+    // when the tile does not fit)
+    if (use_lds)
+        for (int idx = tid; idx < nseg * ncb; idx += kBlock) {
+            const int sg = idx / ncb;
+            const int c = idx - sg * ncb;
+            cst[sg][c] = cst[sg][c] - seg_gb[sg] + seg_off[sg];
         }
-        cst[sg][c] = v;
-    }
     // own row of every own particle, when they fit the table
     const bool rows_tab = kLean && own_total <= static_cast<uint32_t>(CAP);
     if (rows_tab)
@@ -754,36 +782,58 @@ __device__ __forceinline__ void tile_body(const SimArgs& a, uint32_t blk)
             for (uint32_t j = static_cast<uint32_t>(tid & 63); j < own_pre[r + 1] - own_pre[r]; j += 64)
                 row_of[own_pre[r] + j] = static_cast<uint8_t>(r);
     if (use_lds) {
-        // each halo row is one contiguous run in HBM and in LDS
-        auto stage = [&](uint32_t idx, uint32_t g) {
+        // Each halo row is one contiguous run in HBM and in LDS.  A thread
+        // stages slots tid, tid + kBlock, ...: it finds every slot's row
+        // first (the searches advance together), then issues all its loads,
+        // then all its LDS stores, so that its loads are in flight at once.
+        constexpr int kIt = (CAP + kBlock - 1) / kBlock;
+        uint32_t sidx[kIt];
+        int sb[kIt];
 #pragma unroll
-            for (int d = 0; d < D; ++d)
-                lpos[d][idx] = static_cast<const T*>(a.x[d])[g];
-            if (TRANSFER) {
-                lsr[idx] = static_cast<const T*>(a.srow)[g];
+        for (int it = 0; it < kIt; ++it) {
+            sidx[it] = static_cast<uint32_t>(tid + it * kBlock);
+            sb[it] = 0;
+        }
+        // last row whose first slot is <= the slot (seg_off[0] = 0); the
+        // range [sb, sb + len) always holds it
+        for (int len = nseg; len > 1;) {
+            const int half = len >> 1;
 #pragma unroll
-                for (int c = 0; c < NS; ++c)
-                    lms[c][idx] = static_cast<const M*>(a.m_mid[c])[g];
-            }
-        };
-        if (kLean && total >= 48u * static_cast<uint32_t>(nseg)) {
-            // long rows: a wave copies whole rows
-            const uint32_t lane = static_cast<uint32_t>(tid & 63);
-            for (int sg = tid >> 6; sg < nseg; sg += kBlock / 64)
-                for (uint32_t j = lane; j < seg_off[sg + 1] - seg_off[sg]; j += 64)
-                    stage(seg_off[sg] + j, seg_gb[sg] + j);
-        } else {
-            // short rows: every thread takes the next slot and finds its row
-            for (uint32_t idx = tid; idx < total; idx += kBlock) {
-                int lo = 0, hi = nseg - 1;
-                while (lo < hi) {
-                    const int mid = (lo + hi + 1) >> 1;
-                    if (seg_off[mid] <= idx)
-                        lo = mid;
-                    else
-                        hi = mid - 1;
+            for (int it = 0; it < kIt; ++it)
+                sb[it] = seg_off[sb[it] + half] <= sidx[it] ? sb[it] + half : sb[it];
+            len -= half;
+        }
+        T vx[kIt][D];
+        T vs[kIt];
+        M vm[kIt][NS];
+#pragma unroll
+        for (int it = 0; it < kIt; ++it) {
+            if (sidx[it] < total) {
+                const uint32_t g = seg_gb[sb[it]] + (sidx[it] - seg_off[sb[it]]);
+#pragma unroll
+                for (int d = 0; d < D; ++d)
+                    vx[it][d] = static_cast<const T*>(a.x[d])[g];
+                if (TRANSFER) {
+                    vs[it] = static_cast<const T*>(a.srow)[g];
+#pragma unroll
+                    for (int c = 0; c < NS; ++c)
+                        vm[it][c] = static_cast<const M*>(a.m_mid[c])[g];
                 }
-                stage(idx, seg_gb[lo] + (idx - seg_off[lo]));
+            }
+        }
+#pragma unroll
+        for (int it = 0; it < kIt; ++it) {
+            if (sidx[it] < total) {
+                const uint32_t idx = sidx[it];
+#pragma unroll
+                for (int d = 0; d < D; ++d)
+                    lpos[d][idx] = vx[it][d];
+                if (TRANSFER) {
+                    lsr[idx] = vs[it];
+#pragma unroll
+                    for (int c = 0; c < NS; ++c)
+                        lms[c][idx] = vm[it][c];
+                }
             }
         }
     }
@@ -921,10 +971,7 @@ __device__ __forceinline__ void tile_body(const SimArgs& a, uint32_t blk)
                             ll[q] = 0;
                         lmax = max(lmax, ll[q]);
                     }
-#pragma unroll
-                    for (int off = 32; off >= 1; off >>= 1)
-                        lmax = max(lmax, static_cast<uint32_t>(__shfl_xor(static_cast<int>(lmax), off, 64)));
-                    lmax = __builtin_amdgcn_readfirstlane(lmax);
+                    lmax = wave_max_u32(lmax);
                     const int nsteps = 32 - __builtin_clz(lmax | 1u);
 #pragma unroll
                     for (int q = 0; q < 3; ++q) {
@@ -971,11 +1018,8 @@ __device__ __forceinline__ void tile_body(const SimArgs& a, uint32_t blk)
                         reinterpret_cast<const char*>(base) + off);
                 };
                 uint32_t kmax = tot;
-#pragma unroll
-                for (int off = 32; off >= 1; off >>= 1)
-                    kmax = max(kmax, static_cast<uint32_t>(__shfl_xor(static_cast<int>(kmax), off, 64)));
-                kmax = __builtin_amdgcn_readfirstlane(kmax);
-                constexpr int kUnroll = D == 3 ? MTPT_CAND_UNROLL_3D : MTPT_CAND_UNROLL_2D;
+                kmax = wave_max_u32(kmax);
+                constexpr int kUnroll = D == 3 ? MTPT_CAND_UNROLL_3D : (PREC == 0 ? MTPT_CAND_UNROLL_2D_F64 : MTPT_CAND_UNROLL_2D);
                 // one candidate at LDS byte offset off (of the T arrays), pair
                 // counted when in
                 auto visit = [&](uint32_t off, bool in, T r2) {
@@ -1009,10 +1053,7 @@ __device__ __forceinline__ void tile_body(const SimArgs& a, uint32_t blk)
                     // mask is candidate k (same rows, same order) within psi
                     uint64_t mk = act ? pmask[i] : 0ull;
                     uint32_t cmax = static_cast<uint32_t>(__builtin_popcountll(mk));
-#pragma unroll
-                    for (int off = 32; off >= 1; off >>= 1)
-                        cmax = max(cmax, static_cast<uint32_t>(__shfl_xor(static_cast<int>(cmax), off, 64)));
-                    cmax = __builtin_amdgcn_readfirstlane(cmax);
+                    cmax = wave_max_u32(cmax);
 #pragma unroll kUnroll
                     for (uint32_t q = 0; q < cmax; ++q) {
                         const bool valid = mk != 0ull;
