@@ -59,6 +59,9 @@ template <int D, int PREC, int NS> struct LdsBudget {
 #ifndef MTPT_CELL_ORDER_2D
 #define MTPT_CELL_ORDER_2D 1
 #endif
+#ifndef MTPT_CELL_ORDER_2D_F32
+#define MTPT_CELL_ORDER_2D_F32 0
+#endif
 // unroll factor of the candidate loop of the tiled passes (the FP64 2-d
 // loops run at lower occupancy and gain from two candidates in flight)
 #ifndef MTPT_CAND_UNROLL_2D

@@ -691,7 +691,7 @@ __device__ __forceinline__ void tile_body(const SimArgs& a, uint32_t blk)
     // that a wave's trip count is near its lanes' mean (the pass's only sum
     // over particles, the pair count, is an integer: the order changes no
     // result).  The FP32 pass's candidates are too cheap to repay the ordering.
-    constexpr bool kCellOrder = D == 2 && PREC == 0 && !TRANSFER && MTPT_CELL_ORDER_2D != 0;
+    constexpr bool kCellOrder = D == 2 && !TRANSFER && (PREC == 0 ? MTPT_CELL_ORDER_2D : MTPT_CELL_ORDER_2D_F32) != 0;
     constexpr int kCells = kCellOrder ? TileLimits<D>::max_x * TileLimits<D>::max_y : 1;
     __shared__ uint16_t ord[kCellOrder ? CAP : 1];
     __shared__ uint8_t ckey[kCells];
@@ -886,9 +886,13 @@ __device__ __forceinline__ void tile_body(const SimArgs& a, uint32_t blk)
 #pragma unroll
     for (int c = 0; c < NS; ++c)
         msum[c] = 0.0;
-    // Every lane of the workgroup runs every pass of this loop (own_total is
-    // uniform), so the wave-wide maxima below see only live lanes.
+    // Every lane of a wave runs every pass the wave takes (own_total is
+    // uniform, and the loop holds no workgroup barrier), so the wave-wide
+    // maxima below see only live lanes.  A wave leaves once all its lanes are
+    // past the last own particle.
     for (uint32_t base = 0; base < own_total; base += kBlock) {
+        if (base + static_cast<uint32_t>(tid & ~63) >= own_total)
+            break;
         const uint32_t t = base + tid;
         const bool act = t < own_total;
         uint32_t tt = act ? t : own_total - 1u;
@@ -937,16 +941,20 @@ __device__ __forceinline__ void tile_body(const SimArgs& a, uint32_t blk)
             if constexpr (!TRANSFER)
                 acc.cnt = 1;   // self; the neighbours are counted from the masks
             // distances from the particle to the y (and z) slabs of the rows
-            // below and above its own, less a rounding margin
-            const int cyc = cell_coord(static_cast<double>(xi[1]), a.glo[1], a.inv_side[1], nc1);
-            const T ylo = static_cast<T>(a.glo[1] + cyc * a.side[1]);
-            const T dyv[3] = {xi[1] - ylo - wmargin_of<T>(a), T(0), ylo + static_cast<T>(a.side[1]) - xi[1] - wmargin_of<T>(a)};
+            // below and above its own, less a rounding margin (for trimming)
+            T dyv[3] = {T(0), T(0), T(0)};
             T dzv[3] = {T(0), T(0), T(0)};
-            if (D == 3) {
-                const int czc = cell_coord(static_cast<double>(xi[2]), a.glo[2], a.inv_side[2], nc2);
-                const T zlo = static_cast<T>(a.glo[2] + czc * a.side[2]);
-                dzv[0] = xi[2] - zlo - wmargin_of<T>(a);
-                dzv[2] = zlo + static_cast<T>(a.side[2]) - xi[2] - wmargin_of<T>(a);
+            if (a.trim_rows) {
+                const int cyc = cell_coord(static_cast<double>(xi[1]), a.glo[1], a.inv_side[1], nc1);
+                const T ylo = static_cast<T>(a.glo[1] + cyc * a.side[1]);
+                dyv[0] = xi[1] - ylo - wmargin_of<T>(a);
+                dyv[2] = ylo + static_cast<T>(a.side[1]) - xi[1] - wmargin_of<T>(a);
+                if (D == 3) {
+                    const int czc = cell_coord(static_cast<double>(xi[2]), a.glo[2], a.inv_side[2], nc2);
+                    const T zlo = static_cast<T>(a.glo[2] + czc * a.side[2]);
+                    dzv[0] = xi[2] - zlo - wmargin_of<T>(a);
+                    dzv[2] = zlo + static_cast<T>(a.side[2]) - xi[2] - wmargin_of<T>(a);
+                }
             }
 #pragma unroll
             for (int pzr = 0; pzr < planes; ++pzr) {
