@@ -642,15 +642,14 @@ __device__ __forceinline__ void scan_row(const SimArgs& a, PX p, PS sr, PM ms, u
 // its slot from the tile's LDS histogram hist; one that leaves takes it from
 // the global histogram, flagged in bit 31 of its rank.
 template <int D, typename T>
-__device__ __forceinline__ void bin_next(const SimArgs& a, uint32_t i, const T* x, const int* tlo,
+__device__ __forceinline__ void bin_next(const SimArgs& a, uint32_t i, const T* x, const T* jump, const int* tlo,
                                          const int* thi, uint32_t* hist)
 {
     uint32_t c = 0, lc = 0;
     bool inside = true;
 #pragma unroll
     for (int k = D - 1; k >= 0; --k) {
-        const T v = reflect_jump<T>(x[k], static_cast<const T*>(a.jmp[k])[i], a.lo[k], a.hi[k], a.lof[k],
-                                    a.hif[k]);
+        const T v = reflect_jump<T>(x[k], jump[k], a.lo[k], a.hi[k], a.lof[k], a.hif[k]);
         static_cast<T*>(a.xt[k])[i] = v;
         const int ck = cell_coord(static_cast<double>(v), a.glo[k], a.inv_side[k], a.nc[k]);
         c = c * static_cast<uint32_t>(a.nc[k]) + static_cast<uint32_t>(ck);
@@ -926,6 +925,16 @@ __device__ __forceinline__ void tile_body(const SimArgs& a, uint32_t blk)
         const int cl = cxr > 0 ? cxr - 1 : 0;
         const int ch = cxr + 2 < ncol ? cxr + 2 : ncol;
         Acc<PREC, NS, TRANSFER> acc;
+        // the particle's jumps and neighbour masks are loaded with its row
+        // sum and masses (issued later, they would wait behind the stores
+        // that precede their use), except in the 3-d three-species pass,
+        // whose registers are the tighter limit
+        constexpr bool kEarly = TRANSFER && kLean;
+        T jv[3] = {T(0), T(0), T(0)};
+        uint64_t mkp[planes];
+#pragma unroll
+        for (int pzr = 0; pzr < planes; ++pzr)
+            mkp[pzr] = 0ull;
         if constexpr (TRANSFER) {
             acc.si = static_cast<const T*>(a.srow)[i];
 #pragma unroll
@@ -933,6 +942,16 @@ __device__ __forceinline__ void tile_body(const SimArgs& a, uint32_t blk)
                 acc.mi[c] = static_cast<const M*>(a.m_mid[c])[i];
                 acc.dl[c] = 0;
                 acc.comp[c] = 0;
+            }
+            if (kEarly && a.fuse_bin) {
+#pragma unroll
+                for (int d = 0; d < D; ++d)
+                    jv[d] = static_cast<const T*>(a.jmp[d])[i];
+            }
+            if (kEarly && mask_ok && act) {
+#pragma unroll
+                for (int pzr = 0; pzr < planes; ++pzr)
+                    mkp[pzr] = a.cmask[static_cast<size_t>(pzr) * static_cast<size_t>(a.n) + i];
             }
         }
         if (use_lds) {
@@ -1059,7 +1078,7 @@ __device__ __forceinline__ void tile_body(const SimArgs& a, uint32_t blk)
                 if (TRANSFER && mask_ok && kmax <= 64u) {
                     // neighbours recorded by the row-sum pass: bit k of the
                     // mask is candidate k (same rows, same order) within psi
-                    uint64_t mk = act ? pmask[i] : 0ull;
+                    uint64_t mk = kEarly ? mkp[pzr] : (act ? pmask[i] : 0ull);
                     uint32_t cmax = static_cast<uint32_t>(__builtin_popcountll(mk));
                     cmax = wave_max_u32(cmax);
 #pragma unroll kUnroll
@@ -1164,7 +1183,12 @@ __device__ __forceinline__ void tile_body(const SimArgs& a, uint32_t blk)
             if (a.fuse_bin) {
                 const int tlo[3] = {x0, y0, tz};
                 const int thi[3] = {x1, y1, tz + 1};
-                bin_next<D, T>(a, i, xi, tlo, thi, hist);
+                if (!kEarly) {
+#pragma unroll
+                    for (int d = 0; d < D; ++d)
+                        jv[d] = static_cast<const T*>(a.jmp[d])[i];
+                }
+                bin_next<D, T>(a, i, xi, jv, tlo, thi, hist);
             }
         }
     }
