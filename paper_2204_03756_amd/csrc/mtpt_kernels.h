@@ -31,21 +31,19 @@ constexpr int kScanItems = 16;       // counts per thread in the scan
 constexpr int kScanTile = kBlock * kScanItems;
 constexpr int kFinalBlock = 1024;    // threads of the finalize kernel
 constexpr uint32_t kScanFold = 2048;  // scans of at most this many tiles skip the top pass
-// bytes of staged particle data per workgroup of the mass-transfer passes
-// (3-d halos hold three planes of cell rows)
 // LDS staging budget (bytes) of a tile of the mass-transfer passes, per
-// dimension, precision and species count.  The 2-d FP32 kernels and the 3-d
-// FP32 one-species kernels are limited by LDS occupancy and take smaller
-// tiles; FP64 and three-species kernels are limited by registers and take
-// larger ones.
+// dimension, precision and species count (3-d halos hold three planes of
+// cell rows).  Chosen by measurement: the FP32 one-species kernels trade
+// workgroups per CU (LDS-limited) against halo overhead per tile; the FP64
+// and three-species kernels are limited by registers and take larger tiles.
 #ifndef MTPT_LDS_BUDGET_2D
-#define MTPT_LDS_BUDGET_2D 16384
+#define MTPT_LDS_BUDGET_2D 20480
 #endif
 #ifndef MTPT_LDS_BUDGET_2D_F64
 #define MTPT_LDS_BUDGET_2D_F64 24576
 #endif
 #ifndef MTPT_LDS_BUDGET_3D
-#define MTPT_LDS_BUDGET_3D 30720
+#define MTPT_LDS_BUDGET_3D 36864
 #endif
 #ifndef MTPT_LDS_BUDGET_3D_WIDE
 #define MTPT_LDS_BUDGET_3D_WIDE 46080
