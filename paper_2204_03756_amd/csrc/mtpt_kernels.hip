@@ -1081,20 +1081,35 @@ __device__ __forceinline__ void tile_body(const SimArgs& a, uint32_t blk)
                     uint64_t mk = kEarly ? mkp[pzr] : (act ? pmask[i] : 0ull);
                     uint32_t cmax = static_cast<uint32_t>(__builtin_popcountll(mk));
                     cmax = wave_max_u32(cmax);
-#pragma unroll kUnroll
-                    for (uint32_t q = 0; q < cmax; ++q) {
-                        const bool valid = mk != 0ull;
-                        const uint32_t k = valid ? static_cast<uint32_t>(__builtin_ctzll(mk)) : 0u;
-                        mk &= mk - 1ull;
+                    // a lane without a neighbour left visits its own slot:
+                    // r^2 = 0 and m_j - m_i = 0 give an increment of exactly
+                    // zero, which only the compensated sum has to skip
+                    auto visit_bit = [&](uint32_t k, bool valid) {
                         const uint32_t off = slot_of(k, valid);
                         T xj[3];
 #pragma unroll
                         for (int d = 0; d < D; ++d)
                             xj[d] = ld(lpos[d], off);
-                        // a lane without a neighbour left visits its own slot:
-                        // r^2 = 0 and m_j - m_i = 0 give an increment of exactly
-                        // zero, which only the compensated sum has to skip
                         visit(off, PREC == 2 ? valid : true, Pair<D, T>::r2(xi, xj));
+                    };
+                    if (kmax <= 32u) {
+                        // every lane's candidates fit the low word
+                        uint32_t m32 = static_cast<uint32_t>(mk);
+#pragma unroll kUnroll
+                        for (uint32_t q = 0; q < cmax; ++q) {
+                            const bool valid = m32 != 0u;
+                            const uint32_t k = valid ? static_cast<uint32_t>(__builtin_ctz(m32)) : 0u;
+                            m32 &= m32 - 1u;
+                            visit_bit(k, valid);
+                        }
+                    } else {
+#pragma unroll kUnroll
+                        for (uint32_t q = 0; q < cmax; ++q) {
+                            const bool valid = mk != 0ull;
+                            const uint32_t k = valid ? static_cast<uint32_t>(__builtin_ctzll(mk)) : 0u;
+                            mk &= mk - 1ull;
+                            visit_bit(k, valid);
+                        }
                     }
                     continue;
                 }
