@@ -471,9 +471,10 @@ __device__ __forceinline__ void place_body(const SimArgs& a, uint32_t blk)
     const int64_t k = k0 + threadIdx.x;
     const bool live = k < a.n;
     const T* xt0 = static_cast<const T*>(a.xt[0]);
-    uint32_t src = 0, kp = 0, c = 0;
+    uint32_t src = 0, kp = 0, b = 0, e = 0;
     T xv[3];
     M mv[3];
+    T jv[3];
     if (live) {
         src = a.perm[k];
 #pragma unroll
@@ -485,14 +486,26 @@ __device__ __forceinline__ void place_body(const SimArgs& a, uint32_t blk)
         for (int s = 0; s < 3; ++s)
             if (s < a.ns)
                 mv[s] = static_cast<const M*>(a.m_src[s])[src];
-        c = cell_index<D, T>(a, xv);
+        const uint32_t c = cell_index<D, T>(a, xv);
+        b = a.starts[c];
+        e = a.starts[c + 1];
         lkx[threadIdx.x] = xv[0];
         lkp[threadIdx.x] = kp;
+        if (a.fuse_bin) {
+            // the jumps of the step after a.step, for the transfer pass's
+            // walk, drawn while the cell's offsets are in flight
+            double z[3], spare;
+            normal_pair(a.seed, a.step + 1, kp, 0u, &z[0], &z[1]);
+            if (D == 3)
+                normal_pair(a.seed, a.step + 1, kp, 1u, &z[2], &spare);
+#pragma unroll
+            for (int d = 0; d < D; ++d)
+                jv[d] = jump_of<T>(z[d], a.sdev, a.drift[d]);
+        }
     }
     __syncthreads();
     if (!live)
         return;
-    const uint32_t b = a.starts[c], e = a.starts[c + 1];
     const uint32_t lo = static_cast<uint32_t>(k0);
     const uint32_t hi = static_cast<uint32_t>(min(k0 + kBlock, a.n));
     const T kx = xv[0];
@@ -520,15 +533,9 @@ __device__ __forceinline__ void place_body(const SimArgs& a, uint32_t blk)
             static_cast<M*>(a.m_mid[s])[dst] = mv[s];
     a.pid_dst[dst] = kp;
     if (a.fuse_bin) {
-        // the jumps of the step after a.step, for the transfer pass's walk
-        // (this pass waits on memory; the arithmetic is hidden there)
-        double z[3], spare;
-        normal_pair(a.seed, a.step + 1, kp, 0u, &z[0], &z[1]);
-        if (D == 3)
-            normal_pair(a.seed, a.step + 1, kp, 1u, &z[2], &spare);
 #pragma unroll
         for (int d = 0; d < D; ++d)
-            static_cast<T*>(a.jmp[d])[dst] = jump_of<T>(z[d], a.sdev, a.drift[d]);
+            static_cast<T*>(a.jmp[d])[dst] = jv[d];
     }
 }
 
