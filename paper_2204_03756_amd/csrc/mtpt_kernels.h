@@ -196,6 +196,9 @@ uint32_t phase_blocks(int ph, const SimArgs& a);
 
 // single-sim launch of a phase
 hipError_t launch_phase(int ph, int dim, int prec, const SimArgs& a, hipStream_t s);
+// PH_PLACE of a, with the PH_FINALIZE of the previous step prev run by one
+// more workgroup of the same launch
+hipError_t launch_place_fin(int dim, int prec, const SimArgs& a, const SimArgs& prev, hipStream_t s);
 // batched launch of a phase over sims that share (dim, prec, ns)
 hipError_t launch_phase_batched(int ph, int dim, int prec, int ns, const Batch& b, hipStream_t s);
 

@@ -1247,12 +1247,14 @@ __device__ __forceinline__ void finalize_body(const SimArgs& a, uint32_t nparts,
     unsigned long long pairs = 0;
     if (mode == 0 && a.recompute_s) {
         unsigned long long p = 0;
+#pragma unroll 8
         for (uint32_t b = threadIdx.x; b < nparts; b += NT)
             p += a.pair_part[b];
         pairs = block_sum<NT, unsigned long long>(p);
     }
     for (int c = 0; c < ns; ++c) {
         double s = 0.0;
+#pragma unroll 8
         for (uint32_t b = threadIdx.x; b < nparts; b += NT)
             s += a.partials[static_cast<size_t>(b) * ns + c];
         const double t = block_sum<NT, double>(s);
@@ -1315,6 +1317,17 @@ __global__ __launch_bounds__(kBlock) void place_kb(Batch b)
     place_body<D, typename Types<PREC>::T, typename Types<PREC>::M>(a, l);
 }
 
+// place_k with one more workgroup, the first, that finalizes the previous
+// step (its totals and pair counters) while the gathers run
+template <int D, int PREC>
+__global__ __launch_bounds__(kBlock) void place_fin_k(SimArgs a, SimArgs prev)
+{
+    if (blockIdx.x == 0) {
+        finalize_body<kBlock>(prev, prev.ntiles, 0);
+        return;
+    }
+    place_body<D, typename Types<PREC>::T, typename Types<PREC>::M>(a, xcd_block(blockIdx.x - 1, gridDim.x - 1));
+}
 template <int D, int PREC>
 __global__ __launch_bounds__(kBlock) void rowsum_k(SimArgs a) { tile_body<D, PREC, 1, false>(a, xcd_block(blockIdx.x, gridDim.x)); }
 template <int D, int PREC>
@@ -1586,6 +1599,21 @@ hipError_t launch_phase(int ph, int dim, int prec, const SimArgs& a, hipStream_t
     case PH_TRANSFER: MTPT_DISPATCH_D_PREC_NS(transfer_k, grid, a); break;
     case PH_FINALIZE: finalize_k<<<1, kFinalBlock, 0, s>>>(a, a.ntiles, 0); break;
     default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_place_fin(int dim, int prec, const SimArgs& a, const SimArgs& prev, hipStream_t s)
+{
+    const uint32_t grid = phase_blocks(PH_PLACE, a) + 1;
+    if (dim == 2) {
+        if (prec == 0) place_fin_k<2, 0><<<grid, kBlock, 0, s>>>(a, prev);
+        else if (prec == 1) place_fin_k<2, 1><<<grid, kBlock, 0, s>>>(a, prev);
+        else place_fin_k<2, 2><<<grid, kBlock, 0, s>>>(a, prev);
+    } else {
+        if (prec == 0) place_fin_k<3, 0><<<grid, kBlock, 0, s>>>(a, prev);
+        else if (prec == 1) place_fin_k<3, 1><<<grid, kBlock, 0, s>>>(a, prev);
+        else place_fin_k<3, 2><<<grid, kBlock, 0, s>>>(a, prev);
     }
     return hipGetLastError();
 }

@@ -273,6 +273,10 @@ struct mtpt_sim {
     bool moving = false;
     bool s_valid = false;
     bool bin_ready = false;   // the last transfer already binned for this step
+    // the last step's totals and counters (PH_FINALIZE) are enqueued with the
+    // next step's place launch, or on their own before anything reads them
+    bool fin_pending = false;
+    SimArgs fin_args{};
     double mass_initial[3]{};
     // profiling
     bool profiling = false;
@@ -435,7 +439,9 @@ SimArgs step_args(const mtpt_sim* s, bool* rowsum_needed)
     return a;
 }
 
-int launch(mtpt_sim* s, int ph, const SimArgs& a)
+// Launch one phase of a sim; with prev (PH_PLACE only) the same launch also
+// finalizes the step that prev describes.
+int launch(mtpt_sim* s, int ph, const SimArgs& a, const SimArgs* prev = nullptr)
 {
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (s->profiling) {
@@ -443,7 +449,10 @@ int launch(mtpt_sim* s, int ph, const SimArgs& a)
         HIP_TRY(hipEventCreate(&e1));
         HIP_TRY(hipEventRecord(e0, s->stream));
     }
-    HIP_TRY(launch_phase(ph, s->q.dim, s->q.prec, a, s->stream));
+    if (prev)
+        HIP_TRY(launch_place_fin(s->q.dim, s->q.prec, a, *prev, s->stream));
+    else
+        HIP_TRY(launch_phase(ph, s->q.dim, s->q.prec, a, s->stream));
     if (s->profiling) {
         HIP_TRY(hipEventRecord(e1, s->stream));
         s->evs.push_back({ph, e0, e1});
@@ -451,9 +460,20 @@ int launch(mtpt_sim* s, int ph, const SimArgs& a)
     return MTPT_OK;
 }
 
+// The pending finalize, on its own.
+int flush_finalize(mtpt_sim* s)
+{
+    if (!s->fin_pending)
+        return MTPT_OK;
+    s->fin_pending = false;
+    return launch(s, PH_FINALIZE, s->fin_args);
+}
+
 // Binning; the bin phase itself is skipped when the previous transfer pass
-// already walked and binned every particle for this step.
-int enqueue_binning(mtpt_sim* s, const SimArgs& a, bool with_bin)
+// already walked and binned every particle for this step.  With prev, the
+// place launch also finalizes the step that prev describes (before this
+// step's row-sum and transfer passes rewrite its partial sums).
+int enqueue_binning(mtpt_sim* s, const SimArgs& a, bool with_bin, const SimArgs* prev = nullptr)
 {
     static const int phases[] = {PH_BIN, PH_SCAN_REDUCE, PH_SCAN_TOP, PH_SCAN_DOWN,
                                  PH_SCATTER, PH_PLACE};
@@ -462,7 +482,7 @@ int enqueue_binning(mtpt_sim* s, const SimArgs& a, bool with_bin)
             continue;
         if (ph == PH_SCAN_TOP && a.scan_fold)
             continue;
-        const int rc = launch(s, ph, a);
+        const int rc = launch(s, ph, a, ph == PH_PLACE ? prev : nullptr);
         if (rc)
             return rc;
     }
@@ -473,8 +493,18 @@ int enqueue_step(mtpt_sim* s)
 {
     bool need_rowsum = false;
     SimArgs a = step_args(s, &need_rowsum);
+    // the previous step's finalize joins this step's place launch when the
+    // step has one (a moving sim whose particles are binned)
+    const bool merge = s->fin_pending && s->moving && s->bin_ready;
+    if (s->fin_pending && !merge) {
+        const int rc = flush_finalize(s);
+        if (rc)
+            return rc;
+    }
     if (s->moving) {
-        const int rc = enqueue_binning(s, a, !s->bin_ready);
+        const SimArgs prev = s->fin_args;
+        s->fin_pending = false;
+        const int rc = enqueue_binning(s, a, !s->bin_ready, merge ? &prev : nullptr);
         if (rc)
             return rc;
     }
@@ -483,12 +513,11 @@ int enqueue_step(mtpt_sim* s)
         if (rc)
             return rc;
     }
-    int rc = launch(s, PH_TRANSFER, a);
+    const int rc = launch(s, PH_TRANSFER, a);
     if (rc)
         return rc;
-    rc = launch(s, PH_FINALIZE, a);
-    if (rc)
-        return rc;
+    s->fin_args = a;
+    s->fin_pending = true;
     s->steps_done += 1;
     if (!s->moving)
         s->s_valid = true;
@@ -499,6 +528,9 @@ int enqueue_step(mtpt_sim* s)
 
 int sync(mtpt_sim* s)
 {
+    const int rc = flush_finalize(s);
+    if (rc)
+        return rc;
     HIP_TRY(hipStreamSynchronize(s->stream));
     return MTPT_OK;
 }
@@ -731,6 +763,10 @@ int mtpt_masses(mtpt_sim* s, double* out)
     if (n == 0)
         return MTPT_OK;
     const size_t bytes = n * s->q.ns * 8;
+    // the totals of the last step decide MTPT_E_NONFINITE below
+    const int rf = flush_finalize(s);
+    if (rf)
+        return rf;
     double* d = static_cast<double*>(s->alloc.get(bytes));
     if (!d)
         return fail(MTPT_E_NOMEM, "staging allocation failed");

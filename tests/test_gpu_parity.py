@@ -167,6 +167,35 @@ def test_static_resume_bitwise(mt):
     assert np.array_equal(a, c)
 
 
+@pytest.mark.parametrize("kind", ["rw2d", "plain2d"])
+def test_stats_read_between_steps(mt, kind):
+    """A step's totals and pair counters are completed either by the next
+    step's first launch or, when something reads them first, on their own:
+    reading them after every step gives the same counters, totals and masses
+    as reading once after the same steps enqueued back to back."""
+    w = W.rw2d(n=30_000, steps=5) if kind == "rw2d" else W.plain2d(n=5000, steps=5)
+    alloc = mt.TorchAllocator("cuda:0")
+    with mt.Sim(w.params, w.x0, w.m0, allocator=alloc) as sim:
+        per = []
+        for _ in range(5):
+            sim.step(1)
+            per.append(sim.stats())
+        ma = sim.masses()
+    with mt.Sim(w.params, w.x0, w.m0, allocator=alloc) as sim:
+        sim.step(2)
+        sim.step(3)
+        mb = sim.masses()
+        sb = sim.stats()
+    sa = per[-1]
+    assert np.array_equal(ma, mb)
+    assert [p["steps_done"] for p in per] == [1, 2, 3, 4, 5]
+    assert sa["steps_done"] == sb["steps_done"] == 5
+    assert sa["pairs_total"] == sb["pairs_total"] and sa["pairs_last"] == sb["pairs_last"]
+    assert sa["pairs_total"] == sum(p["pairs_last"] for p in per)
+    assert np.array_equal(np.asarray(sa["mass_total"]), np.asarray(sb["mass_total"]))
+    assert all(p["pairs_last"] > 0 for p in per)
+
+
 # ------------------------------------------------------------ edge cases --
 def test_edge_cases(mt, oracle):
     say("  edge: n=0")
