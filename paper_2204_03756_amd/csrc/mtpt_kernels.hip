@@ -646,11 +646,12 @@ __device__ __forceinline__ void scan_row(const SimArgs& a, PX p, PS sr, PM ms, u
 // sorted particle i for the step after a.step (the next step's binning,
 // done while its position is in registers).
 // A particle that stays inside the tile (cells [tlo, thi) per axis) takes
-// its slot from the tile's LDS histogram hist; one that leaves takes it from
-// the global histogram, flagged in bit 31 of its rank.
+// its slot from the tile's LDS histogram hist (two 16-bit counts per word,
+// used when the tile holds fewer than 65536 particles: tile_hist); one that
+// leaves takes it from the global histogram, flagged in bit 31 of its rank.
 template <int D, typename T>
 __device__ __forceinline__ void bin_next(const SimArgs& a, uint32_t i, const T* x, const T* jump, const int* tlo,
-                                         const int* thi, uint32_t* hist)
+                                         const int* thi, uint32_t* hist, bool tile_hist)
 {
     uint32_t c = 0, lc = 0;
     bool inside = true;
@@ -664,7 +665,14 @@ __device__ __forceinline__ void bin_next(const SimArgs& a, uint32_t i, const T* 
         lc = lc * static_cast<uint32_t>(thi[k] - tlo[k]) + static_cast<uint32_t>(ck - tlo[k]);
     }
     a.cell[i] = c;
-    a.rank[i] = inside ? atomicAdd(&hist[lc], 1u) : (0x80000000u | atomicAdd(&a.counts[c], 1u));
+    uint32_t rank;
+    if (inside && tile_hist) {
+        const uint32_t sh = (lc & 1u) << 4;
+        rank = (atomicAdd(&hist[lc >> 1], 1u << sh) >> sh) & 0xFFFFu;
+    } else {
+        rank = 0x80000000u | atomicAdd(&a.counts[c], 1u);
+    }
+    a.rank[i] = rank;
 }
 
 // One tile: tx * ty cells of plane tz.  Halo rows (cells xa..xb-1 of rows
@@ -702,7 +710,9 @@ __device__ __forceinline__ void tile_body(const SimArgs& a, uint32_t blk)
     __shared__ uint16_t ord[kCellOrder ? CAP : 1];
     __shared__ uint8_t ckey[kCells];
     __shared__ uint32_t obase[64];
-    constexpr int kHist = TRANSFER ? TileLimits<D>::max_x * TileLimits<D>::max_y : 1;
+    // per-cell counts of the particles that stay in the tile, two 16-bit
+    // counts per word
+    constexpr int kHist = TRANSFER ? (TileLimits<D>::max_x * TileLimits<D>::max_y + 1) / 2 : 1;
     __shared__ uint32_t hist[kHist];
 
     const int tid = threadIdx.x;
@@ -724,7 +734,7 @@ __device__ __forceinline__ void tile_body(const SimArgs& a, uint32_t blk)
     const int ncol = xb - xa;
     const int tw = x1 - x0;
     if (TRANSFER && a.fuse_bin)
-        for (int k = tid; k < tw * nrow; k += kBlock)
+        for (int k = tid; k < (tw * nrow + 1) / 2; k += kBlock)
             hist[k] = 0u;
 
     // every cell boundary of the halo rows in one round of loads, as global
@@ -1210,7 +1220,7 @@ __device__ __forceinline__ void tile_body(const SimArgs& a, uint32_t blk)
                     for (int d = 0; d < D; ++d)
                         jv[d] = static_cast<const T*>(a.jmp[d])[i];
                 }
-                bin_next<D, T>(a, i, xi, jv, tlo, thi, hist);
+                bin_next<D, T>(a, i, xi, jv, tlo, thi, hist, own_total < 65536u);
             }
         }
     }
@@ -1220,7 +1230,7 @@ __device__ __forceinline__ void tile_body(const SimArgs& a, uint32_t blk)
         for (int k = tid; k < tw * nrow; k += kBlock) {
             const int ry = k / tw;
             const uint32_t c = (static_cast<uint32_t>(D == 3 ? tz : 0) * nc1 + (y0 + ry)) * nc0 + x0 + (k - ry * tw);
-            a.tcounts[c] = hist[k];
+            a.tcounts[c] = (hist[k >> 1] >> ((k & 1) << 4)) & 0xFFFFu;
         }
     }
     if constexpr (!TRANSFER) {
