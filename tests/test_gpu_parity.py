@@ -241,6 +241,26 @@ def test_edge_cases(mt, oracle):
             assert st["pairs_total"] == int(ref.pairs.sum())
 
 
+@pytest.mark.parametrize("prec", [W.FP64, W.FP32W_FP64ACC])
+def test_dense_tile_global_histogram(mt, oracle, prec):
+    """70000 particles inside the cells of one tile (a small psi in a large box
+    makes the tiles 24 x 24 cells): the tile overflows the LDS, so both passes
+    read its rows from global memory, and the transfer pass bins its
+    particles through the global histogram, since the tile's LDS histogram
+    holds 16-bit counts."""
+    rng = np.random.default_rng(21)
+    n = 70_000
+    x0 = 0.2 + rng.random((n, 2)) * 4.1
+    p = W.Params(dim=2, n=n, lo=[0, 0, 0], hi=[100, 100, 0], d_rw=0.001, d_mt=0.01, dt=0.1, seed=23,
+                 precision=prec)
+    w = W.Workload("dense-tile", p, x0, rng.random((1, n)), 3)
+    m, x, st = gpu_run(mt, w, 3)
+    ref = oracle_run(oracle, w, 3)
+    assert np.array_equal(x, ref.x)
+    assert normwise(m, ref.m) <= TOL[prec]
+    assert st["pairs_total"] == int(ref.pairs.sum())
+
+
 # --------------------------------------------------------------- full size --
 def test_rw2d_full_size_first_steps(mt, oracle):
     """4e6 particles: the first two steps against the oracle, then 100 steps
