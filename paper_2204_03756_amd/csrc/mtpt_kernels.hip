@@ -697,10 +697,10 @@ __device__ __forceinline__ void tile_body(const SimArgs& a, uint32_t blk)
     __shared__ uint32_t cst[kSegs][TileLimits<D>::cols];
     __shared__ uint32_t own_gb[kRows];
     __shared__ uint32_t own_pre[kRows + 1];
-    // the own-row table, except in the 3-d three-species transfer pass (its
-    // registers would cost that pass a wave per SIMD)
-    constexpr bool kLean = !(D == 3 && NS == 3 && TRANSFER);
-    __shared__ uint8_t row_of[kLean ? CAP : 1];   // own row of each own particle
+    // the own-row table in 2-d; in 3-d its bytes would cost both passes a
+    // workgroup per CU, and a search over at most 16 rows finds the row
+    constexpr bool kRowTab = D == 2 || MTPT_ROW_TABLE_3D != 0;
+    __shared__ uint8_t row_of[kRowTab ? CAP : 1];   // own row of each own particle
     // 2-d FP64 row-sum pass: own cells in order of their candidate count, so
     // that a wave's trip count is near its lanes' mean (the pass's only sum
     // over particles, the pair count, is an integer: the order changes no
@@ -792,7 +792,7 @@ __device__ __forceinline__ void tile_body(const SimArgs& a, uint32_t blk)
             cst[sg][c] = cst[sg][c] - seg_gb[sg] + seg_off[sg];
         }
     // own row of every own particle, when they fit the table
-    const bool rows_tab = kLean && own_total <= static_cast<uint32_t>(CAP);
+    const bool rows_tab = kRowTab && own_total <= static_cast<uint32_t>(CAP);
     if (rows_tab)
         for (int r = tid >> 6; r < nrow; r += kBlock / 64)
             for (uint32_t j = static_cast<uint32_t>(tid & 63); j < own_pre[r + 1] - own_pre[r]; j += 64)
@@ -918,7 +918,7 @@ __device__ __forceinline__ void tile_body(const SimArgs& a, uint32_t blk)
         }
         int r = 0;
         if (rows_tab) {
-            r = row_of[kLean ? tt : 0u];
+            r = row_of[kRowTab ? tt : 0u];
         } else {
             int hi = nrow - 1;
             while (r < hi) {
@@ -946,7 +946,7 @@ __device__ __forceinline__ void tile_body(const SimArgs& a, uint32_t blk)
         // sum and masses (issued later, they would wait behind the stores
         // that precede their use), except in the 3-d three-species pass,
         // whose registers are the tighter limit
-        constexpr bool kEarly = TRANSFER && kLean;
+        constexpr bool kEarly = TRANSFER && !(D == 3 && NS == 3);
         T jv[3] = {T(0), T(0), T(0)};
         uint64_t mkp[planes];
 #pragma unroll
