@@ -81,15 +81,21 @@ template <int D, int PREC, int NS> struct LdsBudget {
 #define MTPT_CAND_UNROLL_3D 4
 #endif
 
-// Largest tile (cells in x and in y) of the mass-transfer passes, the halo
+// Largest tile (cells in x, y and z) of the mass-transfer passes, the halo
 // cell rows it spans and the cell boundaries kept per halo row.
 template <int D> struct TileLimits {
-    static constexpr int max_x = D == 2 ? 24 : 16;
-    static constexpr int max_y = D == 2 ? 24 : 16;
-    static constexpr int segs = (D == 3 ? 3 : 1) * (max_y + 2);
+    static constexpr int max_x = D == 2 ? 24 : 12;
+    static constexpr int max_y = D == 2 ? 24 : 6;
+    static constexpr int max_z = D == 2 ? 1 : 6;
+    static constexpr int segs = (D == 3 ? max_z + 2 : 1) * (max_y + 2);
     static constexpr int cols = max_x + 3;
 };
-inline int tile_max(int dim) { return dim == 2 ? TileLimits<2>::max_x : TileLimits<3>::max_x; }
+inline int tile_max(int dim, int axis)
+{
+    if (dim == 2)
+        return axis == 0 ? TileLimits<2>::max_x : axis == 1 ? TileLimits<2>::max_y : 1;
+    return axis == 0 ? TileLimits<3>::max_x : axis == 1 ? TileLimits<3>::max_y : TileLimits<3>::max_z;
+}
 
 struct DevStats {
     unsigned long long pairs_last;   // pairs of the last step
@@ -112,8 +118,9 @@ struct SimArgs {
     double inv_side[3];
     int32_t nc[3];
     uint32_t ncells;
-    // tiles of the mass-transfer passes: tx * ty cells of one z plane
-    int32_t tile[2];
+    // tiles of the mass-transfer passes: tx * ty * tz cells (tz = 1 in 2-d),
+    // numbered x fastest
+    int32_t tile[3];
     uint32_t tiles_x, tiles_y, ntiles;
     // box and walk
     double lo[3], hi[3];

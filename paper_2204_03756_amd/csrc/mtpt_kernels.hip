@@ -675,10 +675,12 @@ __device__ __forceinline__ void bin_next(const SimArgs& a, uint32_t i, const T* 
     a.rank[i] = rank;
 }
 
-// One tile: tx * ty cells of plane tz.  Halo rows (cells xa..xb-1 of rows
-// y0-1..y1 of planes tz-1..tz+1) are staged in LDS with the offsets of their
-// cell boundaries; a particle in cell cx visits cells cx-1..cx+1 of each of
-// its 3^(d-1) neighbouring rows, restricted to the x-window.
+// One tile: tx * ty * tz cells (tz = 1 in 2-d).  Halo rows (cells xa..xb-1
+// of rows y0-1..y1 of planes z0-1..z1) are staged in LDS with the offsets of
+// their cell boundaries; a particle in cell cx visits cells cx-1..cx+1 of
+// each of its 3^(d-1) neighbouring rows, restricted to the x-window.  The
+// tile's own rows are numbered y fastest: own row r is row r % nrow of own
+// plane r / nrow.
 template <int D, int PREC, int NS, bool TRANSFER>
 __device__ __forceinline__ void tile_body(const SimArgs& a, uint32_t blk)
 {
@@ -691,14 +693,14 @@ __device__ __forceinline__ void tile_body(const SimArgs& a, uint32_t blk)
     __shared__ T lsr[SCAP];
     __shared__ M lms[NS][SCAP];
     constexpr int kSegs = TileLimits<D>::segs;
-    constexpr int kRows = TileLimits<D>::max_y;
+    constexpr int kRows = TileLimits<D>::max_y * TileLimits<D>::max_z;   // own rows
     __shared__ uint32_t seg_gb[kSegs];
     __shared__ uint32_t seg_off[kSegs + 1];
     __shared__ uint32_t cst[kSegs][TileLimits<D>::cols];
     __shared__ uint32_t own_gb[kRows];
     __shared__ uint32_t own_pre[kRows + 1];
     // the own-row table in 2-d; in 3-d its bytes would cost both passes a
-    // workgroup per CU, and a search over at most 16 rows finds the row
+    // workgroup per CU, and a search over at most 36 own rows finds the row
     constexpr bool kRowTab = D == 2 || MTPT_ROW_TABLE_3D != 0;
     __shared__ uint8_t row_of[kRowTab ? CAP : 1];   // own row of each own particle
     // 2-d FP64 row-sum pass: own cells in order of their candidate count, so
@@ -712,29 +714,34 @@ __device__ __forceinline__ void tile_body(const SimArgs& a, uint32_t blk)
     __shared__ uint32_t obase[64];
     // per-cell counts of the particles that stay in the tile, two 16-bit
     // counts per word
-    constexpr int kHist = TRANSFER ? (TileLimits<D>::max_x * TileLimits<D>::max_y + 1) / 2 : 1;
+    constexpr int kHist = TRANSFER ? (TileLimits<D>::max_x * kRows + 1) / 2 : 1;
     __shared__ uint32_t hist[kHist];
 
     const int tid = threadIdx.x;
     const int nc0 = a.nc[0], nc1 = a.nc[1], nc2 = a.nc[2];
-    const uint32_t per_plane = a.tiles_x * a.tiles_y;
-    const int tz = static_cast<int>(blk / per_plane);
-    const uint32_t rem = blk - static_cast<uint32_t>(tz) * per_plane;
+    const uint32_t per_slab = a.tiles_x * a.tiles_y;
+    const int tzi = static_cast<int>(blk / per_slab);
+    const uint32_t rem = blk - static_cast<uint32_t>(tzi) * per_slab;
     const int tyi = static_cast<int>(rem / a.tiles_x);
     const int txi = static_cast<int>(rem - static_cast<uint32_t>(tyi) * a.tiles_x);
     const int x0 = txi * a.tile[0];
     const int x1 = min(x0 + a.tile[0], nc0);
     const int y0 = tyi * a.tile[1];
     const int y1 = min(y0 + a.tile[1], nc1);
-    const int nrow = y1 - y0;
-    const int rows = nrow + 2;
-    const int nseg = rows * planes;
+    const int z0 = D == 3 ? tzi * a.tile[2] : 0;
+    const int z1 = D == 3 ? min(z0 + a.tile[2], nc2) : 1;
+    const int nrow = y1 - y0;                      // own rows per own plane
+    const int nown = nrow * (z1 - z0);             // own rows
+    const int rows = nrow + 2;                     // halo rows per halo plane
+    const int nseg = rows * (D == 3 ? z1 - z0 + 2 : 1);
+    // halo row of own row r
+    auto srow = [nrow, rows](int r) { return D == 3 ? (r / nrow + 1) * rows + r % nrow + 1 : r + 1; };
     const int xa = x0 > 0 ? x0 - 1 : 0;
     const int xb = x1 < nc0 ? x1 + 1 : nc0;
     const int ncol = xb - xa;
     const int tw = x1 - x0;
     if (TRANSFER && a.fuse_bin)
-        for (int k = tid; k < (tw * nrow + 1) / 2; k += kBlock)
+        for (int k = tid; k < (tw * nown + 1) / 2; k += kBlock)
             hist[k] = 0u;
 
     // every cell boundary of the halo rows in one round of loads, as global
@@ -744,7 +751,7 @@ __device__ __forceinline__ void tile_body(const SimArgs& a, uint32_t blk)
     for (int idx = tid; idx < nseg * ncb; idx += kBlock) {
         const int sg = idx / ncb;
         const int c = idx - sg * ncb;
-        const int pz = D == 3 ? tz - 1 + sg / rows : 0;
+        const int pz = D == 3 ? z0 - 1 + sg / rows : 0;
         const int py = y0 - 1 + sg % rows;
         uint32_t v = 0;
         if (py >= 0 && py < nc1 && pz >= 0 && pz < nc2)
@@ -763,20 +770,19 @@ __device__ __forceinline__ void tile_body(const SimArgs& a, uint32_t blk)
         seg_off[tid] = soff;
     if (tid == 0)
         seg_off[nseg] = total;
-    // own row r is halo row r + 1 of the middle plane
-    const int smid = (planes / 2) * rows + 1;
     uint32_t olen = 0;
-    if (tid < nrow) {
-        const uint32_t gb = cst[smid + tid][x0 - xa];
-        olen = cst[smid + tid][x1 - xa] - gb;
+    if (tid < nown) {
+        const int sr = srow(tid);
+        const uint32_t gb = cst[sr][x0 - xa];
+        olen = cst[sr][x1 - xa] - gb;
         own_gb[tid] = gb;
     }
     uint32_t own_total;
     const uint32_t ooff = block_excl_scan(olen, &own_total);
-    if (tid < nrow)
+    if (tid < nown)
         own_pre[tid] = ooff;
     if (tid == 0)
-        own_pre[nrow] = own_total;
+        own_pre[nown] = own_total;
     __syncthreads();
 
     const bool use_lds = total <= static_cast<uint32_t>(CAP);
@@ -794,7 +800,7 @@ __device__ __forceinline__ void tile_body(const SimArgs& a, uint32_t blk)
     // own row of every own particle, when they fit the table
     const bool rows_tab = kRowTab && own_total <= static_cast<uint32_t>(CAP);
     if (rows_tab)
-        for (int r = tid >> 6; r < nrow; r += kBlock / 64)
+        for (int r = tid >> 6; r < nown; r += kBlock / 64)
             for (uint32_t j = static_cast<uint32_t>(tid & 63); j < own_pre[r + 1] - own_pre[r]; j += 64)
                 row_of[own_pre[r] + j] = static_cast<uint8_t>(r);
     if (use_lds) {
@@ -920,7 +926,7 @@ __device__ __forceinline__ void tile_body(const SimArgs& a, uint32_t blk)
         if (rows_tab) {
             r = row_of[kRowTab ? tt : 0u];
         } else {
-            int hi = nrow - 1;
+            int hi = nown - 1;
             while (r < hi) {
                 const int mid = (r + hi + 1) >> 1;
                 if (own_pre[mid] <= tt)
@@ -932,8 +938,10 @@ __device__ __forceinline__ void tile_body(const SimArgs& a, uint32_t blk)
         const uint32_t i = own_gb[r] + (tt - own_pre[r]);
         // the particle's LDS slot; its own position from there when the lanes
         // are permuted (cell order), else a coalesced global load
-        const int smid0 = (planes == 3 ? rows : 0) + r + 1;
+        const int smid0 = srow(r);
         const uint32_t lself = i - seg_gb[smid0] + seg_off[smid0];
+        // first halo row of the particle's lowest candidate plane
+        const int rbase = D == 3 ? (r / nrow) * rows + r % nrow : r;
         T xi[3];
 #pragma unroll
         for (int d = 0; d < D; ++d)
@@ -994,7 +1002,7 @@ __device__ __forceinline__ void tile_body(const SimArgs& a, uint32_t blk)
             }
 #pragma unroll
             for (int pzr = 0; pzr < planes; ++pzr) {
-                const int s0 = pzr * rows + r;
+                const int s0 = rbase + pzr * rows;
                 uint32_t b0 = cst[s0][cl], l0 = cst[s0][ch] - b0;
                 uint32_t b1 = cst[s0 + 1][cl], l1 = cst[s0 + 1][ch] - b1;
                 uint32_t b2 = cst[s0 + 2][cl], l2 = cst[s0 + 2][ch] - b2;
@@ -1175,7 +1183,7 @@ __device__ __forceinline__ void tile_body(const SimArgs& a, uint32_t blk)
             for (int pzr = 0; pzr < planes; ++pzr) {
 #pragma unroll
                 for (int dy = 0; dy < 3; ++dy) {
-                    const int sg = pzr * rows + r + dy;
+                    const int sg = rbase + pzr * rows + dy;
                     const uint32_t b = cst[sg][cl];
                     const uint32_t e = act ? cst[sg][ch] : b;
                     T xlo, xhi;
@@ -1213,8 +1221,8 @@ __device__ __forceinline__ void tile_body(const SimArgs& a, uint32_t blk)
                 msum[c] += static_cast<double>(st);
             }
             if (a.fuse_bin) {
-                const int tlo[3] = {x0, y0, tz};
-                const int thi[3] = {x1, y1, tz + 1};
+                const int tlo[3] = {x0, y0, z0};
+                const int thi[3] = {x1, y1, z1};
                 if (!kEarly) {
 #pragma unroll
                     for (int d = 0; d < D; ++d)
@@ -1227,9 +1235,9 @@ __device__ __forceinline__ void tile_body(const SimArgs& a, uint32_t blk)
     if (TRANSFER && a.fuse_bin) {
         // counts of the tile's cells from the particles that stayed in it
         __syncthreads();
-        for (int k = tid; k < tw * nrow; k += kBlock) {
-            const int ry = k / tw;
-            const uint32_t c = (static_cast<uint32_t>(D == 3 ? tz : 0) * nc1 + (y0 + ry)) * nc0 + x0 + (k - ry * tw);
+        for (int k = tid; k < tw * nown; k += kBlock) {
+            const int rr = k / tw;   // own row, y fastest
+            const uint32_t c = (static_cast<uint32_t>(z0 + rr / nrow) * nc1 + (y0 + rr % nrow)) * nc0 + x0 + (k - rr * tw);
             a.tcounts[c] = (hist[k >> 1] >> ((k & 1) << 4)) & 0xFFFFu;
         }
     }

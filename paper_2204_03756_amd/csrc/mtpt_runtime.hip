@@ -82,7 +82,7 @@ struct Plan {
     double inv_side[3] = {0, 0, 0};
     uint32_t ncells = 1;
     uint32_t scan_blocks = 1, part_blocks = 0;
-    int tile[2] = {1, 1};
+    int tile[3] = {1, 1, 1};
     uint32_t tiles_x = 1, tiles_y = 1, ntiles = 0;
     bool trim_rows = false;
     size_t tsz = 8, msz = 8;
@@ -178,31 +178,56 @@ Plan make_plan(const mtpt_params& p)
     }
     q.scan_blocks = static_cast<uint32_t>((static_cast<uint64_t>(q.ncells) + 1 + kScanTile - 1) / kScanTile);
     q.part_blocks = static_cast<uint32_t>((q.n + kBlock - 1) / kBlock);
-    // tiles of the mass-transfer passes: about 640 own particles, and the
-    // tile plus its one-cell halo expected to fill at most 1/1.25 of the LDS
-    // staging capacity (a fuller tile falls back to global reads)
+    // tiles of the mass-transfer passes, the tile plus its one-cell halo
+    // expected to fill at most 1/1.25 of the LDS staging capacity (a fuller
+    // tile falls back to global reads).  2-d: about 640 own particles, square.
+    // 3-d: the shape within the limits of least estimated cost per own
+    // particle: passes of 256 lanes over the own particles (with a margin of
+    // two standard deviations of their count), staging of the halo and a
+    // fixed setup, in units of one lane's candidate loop.
     {
         const double rho_c = static_cast<double>(q.n) / static_cast<double>(q.ncells);
-        const int planes = q.dim == 3 ? 3 : 1;
         const double cap = static_cast<double>(tile_capacity(q.dim, q.prec, q.ns)) / 1.25;
 #ifndef MTPT_TILE_OWN
 #define MTPT_TILE_OWN 640.0
 #endif
-        const double cells_own = std::max(1.0, MTPT_TILE_OWN / std::max(rho_c, 1e-9));
-        int t = static_cast<int>(std::lround(std::sqrt(cells_own)));
-        int tx = std::max(1, std::min(t, std::min(q.nc[0], tile_max(q.dim))));
-        int ty = std::max(1, std::min(t, std::min(q.nc[1], tile_max(q.dim))));
-        while ((tx + 2.0) * (ty + 2.0) * planes * rho_c > cap && (tx > 1 || ty > 1)) {
-            if (tx >= ty)
-                --tx;
-            else
-                --ty;
+        int tx = 1, ty = 1, tz = 1;
+        if (q.dim == 2) {
+            const double cells_own = std::max(1.0, MTPT_TILE_OWN / std::max(rho_c, 1e-9));
+            const int t = static_cast<int>(std::lround(std::sqrt(cells_own)));
+            tx = std::max(1, std::min(t, std::min(q.nc[0], tile_max(2, 0))));
+            ty = std::max(1, std::min(t, std::min(q.nc[1], tile_max(2, 1))));
+            while ((tx + 2.0) * (ty + 2.0) * rho_c > cap && (tx > 1 || ty > 1)) {
+                if (tx >= ty)
+                    --tx;
+                else
+                    --ty;
+            }
+        } else {
+            double best = 0.0;
+            for (int z = 1; z <= std::min(q.nc[2], tile_max(3, 2)); ++z)
+                for (int y = 1; y <= std::min(q.nc[1], tile_max(3, 1)); ++y)
+                    for (int x = 1; x <= std::min(q.nc[0], tile_max(3, 0)); ++x) {
+                        const double halo = (x + 2.0) * (y + 2.0) * (z + 2.0) * rho_c;
+                        if (halo > cap && !(x == 1 && y == 1 && z == 1))
+                            continue;
+                        const double own = std::max(1e-9, x * y * static_cast<double>(z) * rho_c);
+                        const double passes = std::ceil((own + 2.0 * std::sqrt(own)) / kBlock);
+                        const double cost = (passes * kBlock + 0.02 * halo + 25.0) / own;
+                        if (best == 0.0 || cost < best) {
+                            best = cost;
+                            tx = x;
+                            ty = y;
+                            tz = z;
+                        }
+                    }
         }
         q.tile[0] = tx;
         q.tile[1] = ty;
+        q.tile[2] = tz;
         q.tiles_x = static_cast<uint32_t>((q.nc[0] + tx - 1) / tx);
         q.tiles_y = static_cast<uint32_t>((q.nc[1] + ty - 1) / ty);
-        q.ntiles = q.tiles_x * q.tiles_y * static_cast<uint32_t>(q.dim == 3 ? q.nc[2] : 1);
+        q.ntiles = q.tiles_x * q.tiles_y * static_cast<uint32_t>(q.dim == 3 ? (q.nc[2] + tz - 1) / tz : 1);
         // rows of three cells long enough that trimming them to the x-window
         // saves more candidates than its two binary searches cost
         q.trim_rows = 3.0 * rho_c >= 12.0;
@@ -338,6 +363,7 @@ SimArgs base_args(const mtpt_sim* s)
     a.ncells = q.ncells;
     a.tile[0] = q.tile[0];
     a.tile[1] = q.tile[1];
+    a.tile[2] = q.tile[2];
     a.tiles_x = q.tiles_x;
     a.tiles_y = q.tiles_y;
     a.ntiles = q.ntiles;
