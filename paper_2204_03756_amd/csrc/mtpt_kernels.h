@@ -43,19 +43,14 @@ constexpr uint32_t kScanFold = 2048;  // scans of at most this many tiles skip t
 #define MTPT_LDS_BUDGET_2D_F64 24576
 #endif
 #ifndef MTPT_LDS_BUDGET_3D
-#define MTPT_LDS_BUDGET_3D 36864
-#endif
-#ifndef MTPT_LDS_BUDGET_3D_KAHAN
-#define MTPT_LDS_BUDGET_3D_KAHAN 35000
+#define MTPT_LDS_BUDGET_3D 35000
 #endif
 #ifndef MTPT_LDS_BUDGET_3D_WIDE
 #define MTPT_LDS_BUDGET_3D_WIDE 46080
 #endif
 template <int D, int PREC, int NS> struct LdsBudget {
-    static constexpr int value =
-        D == 3 ? (PREC != 0 && NS == 1 ? (PREC == 2 ? MTPT_LDS_BUDGET_3D_KAHAN : MTPT_LDS_BUDGET_3D)
-                                       : MTPT_LDS_BUDGET_3D_WIDE)
-               : (PREC == 0 ? MTPT_LDS_BUDGET_2D_F64 : MTPT_LDS_BUDGET_2D);
+    static constexpr int value = D == 3 ? (PREC != 0 && NS == 1 ? MTPT_LDS_BUDGET_3D : MTPT_LDS_BUDGET_3D_WIDE)
+                                        : (PREC == 0 ? MTPT_LDS_BUDGET_2D_F64 : MTPT_LDS_BUDGET_2D);
 };
 // 3-d tiled passes keep a table of each own particle's row (else a search)
 #ifndef MTPT_ROW_TABLE_3D
