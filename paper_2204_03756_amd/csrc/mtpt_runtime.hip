@@ -182,14 +182,18 @@ Plan make_plan(const mtpt_params& p)
     // expected to fill at most 1/1.25 of the LDS staging capacity (a fuller
     // tile falls back to global reads).  2-d: about 640 own particles, square.
     // 3-d: the shape within the limits of least estimated cost per own
-    // particle: passes of 256 lanes over the own particles (with a margin of
-    // two standard deviations of their count), staging of the halo and a
-    // fixed setup, in units of one lane's candidate loop.
+    // particle: wave passes (64 lanes; a wave with no particle left leaves)
+    // over the own particles (with a margin of two standard deviations of
+    // their count), staging of the halo and a fixed setup, in units of one
+    // lane's candidate loop.
     {
         const double rho_c = static_cast<double>(q.n) / static_cast<double>(q.ncells);
         const double cap = static_cast<double>(tile_capacity(q.dim, q.prec, q.ns)) / 1.25;
 #ifndef MTPT_TILE_OWN
 #define MTPT_TILE_OWN 640.0
+#endif
+#ifndef MTPT_TILE_LANES
+#define MTPT_TILE_LANES 64.0
 #endif
         int tx = 1, ty = 1, tz = 1;
         if (q.dim == 2) {
@@ -212,8 +216,8 @@ Plan make_plan(const mtpt_params& p)
                         if (halo > cap && !(x == 1 && y == 1 && z == 1))
                             continue;
                         const double own = std::max(1e-9, x * y * static_cast<double>(z) * rho_c);
-                        const double passes = std::ceil((own + 2.0 * std::sqrt(own)) / kBlock);
-                        const double cost = (passes * kBlock + 0.02 * halo + 25.0) / own;
+                        const double passes = std::ceil((own + 2.0 * std::sqrt(own)) / MTPT_TILE_LANES);
+                        const double cost = (passes * MTPT_TILE_LANES + 0.02 * halo + 25.0) / own;
                         if (best == 0.0 || cost < best) {
                             best = cost;
                             tx = x;
