@@ -27,7 +27,10 @@
 namespace mtpt {
 
 constexpr int kBlock = 256;          // threads per workgroup, 4 wave64s
-constexpr int kScanItems = 16;       // counts per thread in the scan
+#ifndef MTPT_SCAN_ITEMS
+#define MTPT_SCAN_ITEMS 8
+#endif
+constexpr int kScanItems = MTPT_SCAN_ITEMS;   // counts per thread in the scan (a multiple of 4)
 constexpr int kScanTile = kBlock * kScanItems;
 constexpr int kFinalBlock = 1024;    // threads of the finalize kernel
 constexpr uint32_t kScanFold = 2048;  // scans of at most this many tiles skip the top pass
