@@ -5,7 +5,8 @@ Sec. 7: the processor bound of Eq. (12) lies at about 1700 cores for the
 runs (L = 100, E = 0.5); slices stop working at 500 cores.  All three follow
 from the pad psi = 6 sqrt(D dt) of Sec. 6.  Sec. 7.1 prints the nearest
 factor pairs of 698 (2 x 349) and 1322 (2 x 661), and says such tilings
-speed up roughly like a 1-d run.  Sec. 2.2 says the runs obey the time-step
+speed up roughly like a 1-d run; it also reports a 1906-fold speedup on 2700
+cores.  Sec. 2.2 says the runs obey the time-step
 optimality condition."""
 import math
 
@@ -38,6 +39,18 @@ def test_processor_bounds_match_the_printed_values():
     assert PL.efficiency(1600, 1000.0, PSI, 2) >= 0.75 > PL.efficiency(2025, 1000.0, PSI, 2)
     with pytest.raises(ValueError):
         PL.max_processors(1.0, 1000.0, PSI, 2)
+
+
+def test_predicted_speedup_meets_the_observed_maximum():
+    # Sec. 7: the 2-d runs (L = 1000) reached a 1906-fold speedup on 2700
+    # cores; Eq. (10) with the same pad predicts it within 2 %, below linear
+    s = PL.speedup(2700, 1000.0, PSI, 2)
+    assert abs(s - 1906.0) / 1906.0 < 0.02
+    assert s < 2700
+    # pads sqrt(2) narrower or twice as wide (the other readings of the
+    # kernel width) miss it by far more
+    for other in (PSI / math.sqrt(2.0), 2.0 * PSI):
+        assert abs(PL.speedup(2700, 1000.0, other, 2) - 1906.0) / 1906.0 > 0.05
 
 
 def test_speedup_limits():
