@@ -5,16 +5,23 @@ Sec. 7: the processor bound of Eq. (12) lies at about 1700 cores for the
 runs (L = 100, E = 0.5); slices stop working at 500 cores.  All three follow
 from the pad psi = 6 sqrt(D dt) of Sec. 6.  Sec. 7.1 prints the nearest
 factor pairs of 698 (2 x 349) and 1322 (2 x 661), and says such tilings
-speed up roughly like a 1-d run; it also reports a 1906-fold speedup on 2700
-cores.  Sec. 2.2 says the runs obey the time-step
-optimality condition."""
+speed up roughly like a 1-d run.  Sec. 7 also reports a 1906-fold speedup
+on 2700 cores, and Sec. 2.2 says the runs obey the time-step optimality
+condition.  The printed values, each with its citation, are read from
+golden/printed_speedup_values.json."""
+import json
 import math
+import os
 
 import pytest
 
 from paper_2204_03756_amd import planner as PL
 
-PSI = PL.pad(1.0, 0.1)
+with open(os.path.join(os.path.dirname(__file__), "golden", "printed_speedup_values.json")) as f:
+    G = json.load(f)
+R2, R3 = G["run_parameters_2d"], G["run_parameters_3d"]
+L2, L3 = R2["L"], R3["L"]
+PSI = PL.pad(R2["D"], R2["dt"])
 
 
 def test_pad_is_six_kernel_deviations():
@@ -24,11 +31,13 @@ def test_pad_is_six_kernel_deviations():
 
 
 def test_processor_bounds_match_the_printed_values():
-    p2 = PL.max_processors(0.75, 1000.0, PSI, 2)
-    p3 = PL.max_processors(0.5, 100.0, PSI, 3)
-    assert 1600 < p2 < 1800          # about 1700
-    assert 300 < p3 < 340            # about 320
-    assert 480 < PL.slices_limit(1000.0, PSI) < 560   # 500
+    b2, b3 = G["processor_bound_2d"], G["processor_bound_3d"]
+    p2 = PL.max_processors(b2["efficiency"], L2, PSI, 2)
+    p3 = PL.max_processors(b3["efficiency"], L3, PSI, 3)
+    # "about" 1700 and 320: within 6 %; slices stop at 500 (L / psi = 527)
+    assert abs(p2 - b2["about"]) / b2["about"] < 0.06
+    assert abs(p3 - b3["about"]) / b3["about"] < 0.06
+    assert abs(PL.slices_limit(L2, PSI) - G["slices_limit"]["cores"]) / G["slices_limit"]["cores"] < 0.06
     # the bound is where the predicted efficiency, Eq. (11), meets the threshold
     assert PL.efficiency(p2, 1000.0, PSI, 2) == pytest.approx(0.75, rel=1e-12)
     assert PL.efficiency(p3, 100.0, PSI, 3) == pytest.approx(0.5, rel=1e-12)
@@ -44,13 +53,14 @@ def test_processor_bounds_match_the_printed_values():
 def test_predicted_speedup_meets_the_observed_maximum():
     # Sec. 7: the 2-d runs (L = 1000) reached a 1906-fold speedup on 2700
     # cores; Eq. (10) with the same pad predicts it within 2 %, below linear
-    s = PL.speedup(2700, 1000.0, PSI, 2)
-    assert abs(s - 1906.0) / 1906.0 < 0.02
-    assert s < 2700
+    o = G["observed_max_speedup_2d"]
+    s = PL.speedup(o["cores"], L2, PSI, 2)
+    assert abs(s - o["speedup"]) / o["speedup"] < 0.02
+    assert s < o["cores"]
     # pads sqrt(2) narrower or twice as wide (the other readings of the
     # kernel width) miss it by far more
     for other in (PSI / math.sqrt(2.0), 2.0 * PSI):
-        assert abs(PL.speedup(2700, 1000.0, other, 2) - 1906.0) / 1906.0 > 0.05
+        assert abs(PL.speedup(o["cores"], L2, other, 2) - o["speedup"]) / o["speedup"] > 0.05
 
 
 def test_speedup_limits():
@@ -68,8 +78,8 @@ def test_speedup_limits():
 
 
 def test_checkerboard_factors_of_the_printed_core_counts():
-    assert PL.checkerboard_factors(698, 1000.0, 1000.0) == (349, 2)
-    assert PL.checkerboard_factors(1322, 1000.0, 1000.0) == (661, 2)
+    for p, f1, f2 in G["nearly_prime_factor_pairs"]["pairs"]:
+        assert PL.checkerboard_factors(p, L2, L2) == (f1, f2)
     assert PL.checkerboard_factors(400, 1000.0, 1000.0) == (20, 20)
     assert PL.checkerboard_factors(1600, 1000.0, 1000.0) == (40, 40)
     assert PL.checkerboard_factors(25, 1000.0, 1000.0) == (5, 5)
@@ -99,7 +109,8 @@ def test_tiling_speedup_reduces_to_the_closed_forms():
             PL.speedup(p, 1000.0, PSI, 1) / (1.0 + 2 * PSI / 1000.0))
     # Sec. 7.1: nearly prime core counts fall below square tilings with fewer
     # cores, and their speedup is much closer to the 1-d curve than to the 2-d one
-    for bad, good in ((698, 400), (1322, 1600)):
+    bads = [p for p, _, _ in G["nearly_prime_factor_pairs"]["pairs"]]
+    for bad, good in zip(bads, G["nearly_prime_factor_pairs"]["square_counts"]):
         sb = PL.tiling_speedup(PL.checkerboard_factors(bad, *box), box, PSI)
         sg = PL.tiling_speedup(PL.checkerboard_factors(good, *box), box, PSI)
         assert sb < sg
@@ -110,7 +121,8 @@ def test_tiling_speedup_reduces_to_the_closed_forms():
 
 def test_time_step_optimality():
     # 2-d runs: N = 1e7 in L = 1000, spacing 0.316, D = 1: bound 0.05 beta <= dt = 0.1
-    assert PL.dt_min(1000.0, 10_000_000, 2, 1.0) == pytest.approx(0.05)
+    assert PL.dt_min(L2, R2["N"], 2, R2["D"]) == pytest.approx(0.05)
+    assert PL.dt_min(L2, R2["N"], 2, R2["D"]) <= R2["dt"]
     # 3-d runs: N = 5e6 in L = 100, spacing 0.585: bound 0.171 beta, so dt = 0.1
     # meets the condition for beta <= 0.58 (the default beta = 1/2) and not at beta = 1
     s3 = 100.0 / 5e6 ** (1.0 / 3.0)
