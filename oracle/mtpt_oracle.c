@@ -88,7 +88,8 @@ double or_uniform52(uint32_t lo_word, uint32_t hi_word)
  *   log m = 2 atanh(s) = 2 (s + s^3/3 + s^5/5 + ...),  s = (m-1)/(m+1),
  * |s| <= 0.1716, truncated after s^23 (remainder < 1e-19 relative);
  *   log u = e ln2 + log m, with ln2 split into a 42-bit head (exact products)
- * and a tail. */
+ * and a tail.  Every multiply-add is one fused multiply-add (fma, rounded
+ * once), every other operation is rounded on its own. */
 static const double OR_LN2_HI = 0.6931471805598903;      /* 0x1.62e42fefa38p-1 */
 static const double OR_LN2_LO = 5.497923018708371e-14;   /* ln2 - OR_LN2_HI   */
 static const double OR_SQRT2 = 1.4142135623730951;
@@ -108,23 +109,33 @@ double or_log(double u)
     double f = m - 1.0;
     double s = f / (2.0 + f);
     double z = s * s;
-    /* t = 1/3 + z (1/5 + z (1/7 + ... + z (1/23))) */
+    /* Horner: t = 1/3 + z (1/5 + z (1/7 + ... + z (1/23))) */
     double t = 1.0 / 23.0;
     for (int k = 10; k >= 1; --k)
-        t = 1.0 / (double)(2 * k + 1) + z * t;
+        t = fma(z, t, 1.0 / (double)(2 * k + 1));
     double ts = s + s;
-    double lm = ts + ts * (z * t);
-    double r = (double)e * OR_LN2_LO;
-    r = r + lm;
-    return (double)e * OR_LN2_HI + r;
+    double lm = fma(ts, z * t, ts);
+    double ed = (double)e;
+    double r = fma(ed, OR_LN2_LO, lm);
+    return fma(ed, OR_LN2_HI, r);
 }
 
 /* sin and cos of 2 pi u for u in (0,1).  4u = q + f (exact), q the quadrant;
  * the angle inside the quadrant is f pi/2, folded to y in [0, pi/4] by
- * sin(pi/2 - y) = cos y.  On [0, pi/4] the Taylor series are nested:
- *   sin y = y (1 - z/(2.3) (1 - z/(4.5) (1 - ... (1 - z/(18.19))))),
- *   cos y =    1 - z/(1.2) (1 - z/(3.4) (1 - ... (1 - z/(17.18)))),  z = y^2.  */
+ * sin(pi/2 - y) = cos y.  On [0, pi/4] the Taylor series through y^19 and
+ * y^18, in z = y^2 by Horner with fused multiply-adds:
+ *   sin y = y (1 - z/3! + z^2/5! - ... - z^9/19!),
+ *   cos y =    1 - z/2! + z^2/4! - ... - z^9/18!.
+ * The coefficients are +-1/n!, each n! exact in FP64 and divided once. */
 static const double OR_HALF_PI = 1.5707963267948966;
+
+static double or_inv_fact(int n)
+{
+    double f = 1.0;
+    for (int k = 2; k <= n; ++k)
+        f = f * (double)k;   /* exact up to 22! */
+    return 1.0 / f;
+}
 
 void or_sincos_2pi(double u, double* s_out, double* c_out)
 {
@@ -141,13 +152,15 @@ void or_sincos_2pi(double u, double* s_out, double* c_out)
         swap = 1;
     }
     double z = y * y;
-    double ts = 1.0, tc = 1.0;
-    for (int k = 9; k >= 1; --k) {
-        double rs = 1.0 / (double)((2 * k) * (2 * k + 1));
-        double rc = 1.0 / (double)((2 * k - 1) * (2 * k));
-        ts = 1.0 - (z * rs) * ts;
-        tc = 1.0 - (z * rc) * tc;
+    /* k = 9 down to 1: coefficient of z^k is (-1)^k / (2k+1)! (sin), (-1)^k / (2k)! (cos) */
+    double ts = -or_inv_fact(19), tc = -or_inv_fact(18);
+    for (int k = 8; k >= 1; --k) {
+        double sg = (k & 1) ? -1.0 : 1.0;
+        ts = fma(z, ts, sg * or_inv_fact(2 * k + 1));
+        tc = fma(z, tc, sg * or_inv_fact(2 * k));
     }
+    ts = fma(z, ts, 1.0);
+    tc = fma(z, tc, 1.0);
     double sy = y * ts, cy = tc;
     double sp = swap ? cy : sy; /* sin of the in-quadrant angle */
     double cp = swap ? sy : cy; /* cos of the in-quadrant angle */

@@ -9,10 +9,11 @@
 //   u1 = (2 k1 + 1) 2^-53 with k1 = word1 << 20 | word0 >> 12, u2 likewise from
 //   words 3 and 2; Box-Muller z0 = r cos(2 pi u2), z1 = r sin(2 pi u2),
 //   r = sqrt(-2 ln u1).  Call 0 gives dimensions 0 and 1, call 1 dimension 2.
-// ln, sin and cos are evaluated from their series with a fixed operation
-// order and FP contraction off, and FP64 division and square root are IEEE
-// correctly rounded, so the jumps are reproducible bit for bit by any
-// implementation of the same recipe.
+// ln, sin and cos are evaluated from their series by Horner with a fixed
+// operation order: each multiply-add an IEEE fused multiply-add, nothing
+// else contracted; FP64 division and square root are IEEE correctly rounded.
+// So the jumps are reproducible bit for bit by any implementation of the
+// same recipe.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -43,12 +44,32 @@ __device__ __forceinline__ double unit_open(uint32_t low, uint32_t high)
     return static_cast<double>(2ull * k + 1ull) * 0x1p-53;
 }
 
-// reciprocals of the odd numbers 3..23 and of the Taylor step products,
-// folded at compile time (IEEE division)
+// reciprocals of the odd numbers 3..23 and of the factorials 2!..19!,
+// folded at compile time (each factorial exact in FP64, one IEEE division)
 constexpr double inv_u(int v) { return 1.0 / static_cast<double>(v); }
+constexpr double inv_fact(int n)
+{
+    double f = 1.0;
+    for (int k = 2; k <= n; ++k)
+        f = f * static_cast<double>(k);
+    return 1.0 / f;
+}
+
+// fma(a, b, c) = a b + c rounded once (IEEE), with the constant addend c
+// taken from scalar registers.  Left to itself the compiler turns a fused
+// multiply-add with a constant addend into two vector moves of the constant
+// and a v_fmac; v_fma_f64 reads the scalar pair directly.  Arithmetic only:
+// the instruction's inputs are read before its result is written.
+__device__ __forceinline__ double fma_sc(double a, double b, double c)
+{
+    double r;
+    asm("v_fma_f64 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "s"(c));
+    return r;
+}
 
 // ln(u), u in (0,1): u = m 2^e, m folded into [sqrt(1/2), sqrt(2)];
-// ln m = 2 atanh(s), s = (m - 1)/(m + 1), series through s^23.
+// ln m = 2 atanh(s), s = (m - 1)/(m + 1), series through s^23 by Horner.
+// Each multiply-add is one IEEE fused multiply-add; nothing else is fused.
 __device__ __forceinline__ double ln_unit(double u)
 {
 #pragma clang fp contract(off)
@@ -64,26 +85,19 @@ __device__ __forceinline__ double ln_unit(double u)
     const double s = f / (2.0 + f);
     const double z = s * s;
     double t = inv_u(23);
-    t = inv_u(21) + z * t;
-    t = inv_u(19) + z * t;
-    t = inv_u(17) + z * t;
-    t = inv_u(15) + z * t;
-    t = inv_u(13) + z * t;
-    t = inv_u(11) + z * t;
-    t = inv_u(9) + z * t;
-    t = inv_u(7) + z * t;
-    t = inv_u(5) + z * t;
-    t = inv_u(3) + z * t;
+#pragma unroll
+    for (int k = 10; k >= 1; --k)
+        t = fma_sc(z, t, inv_u(2 * k + 1));
     const double s2 = s + s;
-    const double lm = s2 + s2 * (z * t);
+    const double lm = __builtin_fma(s2, z * t, s2);
     const double ed = static_cast<double>(e);
-    double r = ed * 5.497923018708371e-14;   // ln 2 minus its 42-bit head
-    r = r + lm;
-    return ed * 0.6931471805598903 + r;      // 42-bit head of ln 2
+    const double r = __builtin_fma(ed, 5.497923018708371e-14, lm);   // ln 2 minus its 42-bit head
+    return __builtin_fma(ed, 0.6931471805598903, r);                // 42-bit head of ln 2
 }
 
 // sin and cos of 2 pi u, u in (0,1): quadrant from 4u, in-quadrant angle
-// folded to [0, pi/4], nested Taylor series through y^19 / y^18.
+// folded to [0, pi/4], Taylor series through y^19 / y^18 in z = y^2 by
+// Horner with fused multiply-adds (coefficients +-1/n!).
 __device__ __forceinline__ void sincos_2pi_unit(double u, double* sn, double* cs)
 {
 #pragma clang fp contract(off)
@@ -93,12 +107,15 @@ __device__ __forceinline__ void sincos_2pi_unit(double u, double* sn, double* cs
     const bool fold = f > 0.5;
     const double y = (fold ? (1.0 - f) : f) * 1.5707963267948966;
     const double z = y * y;
-    double ts = 1.0, tc = 1.0;
+    double ts = -inv_fact(19), tc = -inv_fact(18);
 #pragma unroll
-    for (int k = 9; k >= 1; --k) {
-        ts = 1.0 - (z * inv_u((2 * k) * (2 * k + 1))) * ts;
-        tc = 1.0 - (z * inv_u((2 * k - 1) * (2 * k))) * tc;
+    for (int k = 8; k >= 1; --k) {
+        const double sg = (k & 1) ? -1.0 : 1.0;
+        ts = fma_sc(z, ts, sg * inv_fact(2 * k + 1));
+        tc = fma_sc(z, tc, sg * inv_fact(2 * k));
     }
+    ts = __builtin_fma(z, ts, 1.0);
+    tc = __builtin_fma(z, tc, 1.0);
     const double sy = y * ts;
     const double cy = tc;
     const double sp = fold ? cy : sy;
