@@ -1025,28 +1025,33 @@ __device__ __forceinline__ void tile_body(const SimArgs& a, uint32_t blk)
                     }
                     lmax = wave_max_u32(lmax);
                     const int nsteps = 32 - __builtin_clz(lmax | 1u);
+                    // per row, the first slot with x >= wlo and the first with
+                    // x > whi, both searched over the whole (x-sorted) row:
+                    // wlo <= whi, so the second is never before the first, and
+                    // the six searches advance together
+                    uint32_t slo[3], nlo[3], shi[3], nhi[3];
 #pragma unroll
                     for (int q = 0; q < 3; ++q) {
-                        // first slot with x >= wlo, then first with x > whi
-                        uint32_t lo = bb[q], n = ll[q];
-                        for (int st = 0; st < nsteps; ++st) {
-                            const uint32_t half = n >> 1;
-                            const uint32_t mid = lo + half;
-                            const bool go = n > 0u && lpos[0][mid < CAP ? mid : CAP - 1] < wlo[q];
-                            lo = go ? mid + 1u : lo;
-                            n = go ? n - half - 1u : half;
+                        slo[q] = shi[q] = bb[q];
+                        nlo[q] = nhi[q] = ll[q];
+                    }
+                    for (int st = 0; st < nsteps; ++st) {
+#pragma unroll
+                        for (int q = 0; q < 3; ++q) {
+                            const uint32_t hl = nlo[q] >> 1, ml = slo[q] + hl;
+                            const uint32_t hh = nhi[q] >> 1, mh = shi[q] + hh;
+                            const bool gl = nlo[q] > 0u && lpos[0][ml < CAP ? ml : CAP - 1] < wlo[q];
+                            const bool gh = nhi[q] > 0u && !(lpos[0][mh < CAP ? mh : CAP - 1] > whi[q]);
+                            slo[q] = gl ? ml + 1u : slo[q];
+                            nlo[q] = gl ? nlo[q] - hl - 1u : hl;
+                            shi[q] = gh ? mh + 1u : shi[q];
+                            nhi[q] = gh ? nhi[q] - hh - 1u : hh;
                         }
-                        uint32_t hi = lo;
-                        n = bb[q] + ll[q] - lo;
-                        for (int st = 0; st < nsteps; ++st) {
-                            const uint32_t half = n >> 1;
-                            const uint32_t mid = hi + half;
-                            const bool go = n > 0u && !(lpos[0][mid < CAP ? mid : CAP - 1] > whi[q]);
-                            hi = go ? mid + 1u : hi;
-                            n = go ? n - half - 1u : half;
-                        }
-                        bb[q] = lo;
-                        ll[q] = hi - lo;
+                    }
+#pragma unroll
+                    for (int q = 0; q < 3; ++q) {
+                        bb[q] = slo[q];
+                        ll[q] = shi[q] - slo[q];
                     }
                     b0 = bb[0]; l0 = ll[0];
                     b1 = bb[1]; l1 = ll[1];
