@@ -32,6 +32,12 @@ constexpr int kBlock = 256;          // threads per workgroup, 4 wave64s
 #endif
 constexpr int kScanItems = MTPT_SCAN_ITEMS;   // counts per thread in the scan (a multiple of 4)
 constexpr int kScanTile = kBlock * kScanItems;
+// rows of three cells holding at least this many particles on average are
+// trimmed to each particle's x-window before its candidate loop (measured:
+// it pays at ~20 per row in 3-d, and costs 20-30 % at 4-6 per row)
+#ifndef MTPT_TRIM_MIN_ROW
+#define MTPT_TRIM_MIN_ROW 12.0
+#endif
 constexpr int kFinalBlock = 1024;    // threads of the finalize kernel
 constexpr uint32_t kScanFold = 2048;  // scans of at most this many tiles skip the top pass
 // LDS staging budget (bytes) of a tile of the mass-transfer passes, per

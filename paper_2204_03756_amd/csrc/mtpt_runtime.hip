@@ -234,7 +234,7 @@ Plan make_plan(const mtpt_params& p)
         q.ntiles = q.tiles_x * q.tiles_y * static_cast<uint32_t>(q.dim == 3 ? (q.nc[2] + tz - 1) / tz : 1);
         // rows of three cells long enough that trimming them to the x-window
         // saves more candidates than its two binary searches cost
-        q.trim_rows = 3.0 * rho_c >= 12.0;
+        q.trim_rows = 3.0 * rho_c >= MTPT_TRIM_MIN_ROW;
     }
     const size_t n = static_cast<size_t>(q.n);
     size_t off = 0;
