@@ -12,6 +12,7 @@
 //   P[2][n]     u32  pid of each sorted slot, two buffers
 //   Srow[n]     T    row sums s_i = sum_j K_ij
 //   cmask[pl][n] u64 neighbour bits of the candidate rows, per plane
+//   cwin[pl][n]  u64 trimmed x-windows of the candidate rows, per plane (trimmed sims only)
 //   cell, rank, perm [n] u32   binning scratch (rank bit 31: left its tile)
 //   counts[], tcounts[], starts[] u32   cell histograms (global atomics;
 //                    per-tile stores) and offsets, tile-padded
@@ -167,6 +168,7 @@ struct SimArgs {
     uint32_t* counts;        // per-cell histogram filled with global atomics
     uint32_t* tcounts;       // per-cell counts of particles that stayed in their tile
     uint64_t* cmask;         // [plane][n] neighbour bits of the candidate rows (row-sum pass)
+    uint64_t* cwin;          // [plane][n] x-windows of the trimmed rows (row-sum pass), or null
     uint32_t* starts;
     uint32_t* bsum;
     double* partials;

@@ -956,10 +956,10 @@ __device__ __forceinline__ void tile_body(const SimArgs& a, uint32_t blk)
         // whose registers are the tighter limit
         constexpr bool kEarly = TRANSFER && !(D == 3 && NS == 3);
         T jv[3] = {T(0), T(0), T(0)};
-        uint64_t mkp[planes];
+        uint64_t mkp[planes], wkp[planes];
 #pragma unroll
         for (int pzr = 0; pzr < planes; ++pzr)
-            mkp[pzr] = 0ull;
+            mkp[pzr] = wkp[pzr] = 0ull;
         if constexpr (TRANSFER) {
             acc.si = static_cast<const T*>(a.srow)[i];
 #pragma unroll
@@ -977,6 +977,11 @@ __device__ __forceinline__ void tile_body(const SimArgs& a, uint32_t blk)
 #pragma unroll
                 for (int pzr = 0; pzr < planes; ++pzr)
                     mkp[pzr] = a.cmask[static_cast<size_t>(pzr) * static_cast<size_t>(a.n) + i];
+            }
+            if (kEarly && use_lds && a.trim_rows && act) {
+#pragma unroll
+                for (int pzr = 0; pzr < planes; ++pzr)
+                    wkp[pzr] = a.cwin[static_cast<size_t>(pzr) * static_cast<size_t>(a.n) + i];
             }
         }
         if (use_lds) {
@@ -1007,51 +1012,80 @@ __device__ __forceinline__ void tile_body(const SimArgs& a, uint32_t blk)
                 uint32_t b1 = cst[s0 + 1][cl], l1 = cst[s0 + 1][ch] - b1;
                 uint32_t b2 = cst[s0 + 2][cl], l2 = cst[s0 + 2][ch] - b2;
                 if (a.trim_rows) {
-                    // x-window of each row from its y/z distance: |dx|^2 <= psi^2 - dy^2 - dz^2
-                    const T dz = dzv[D == 3 ? pzr : 1] > T(0) ? dzv[D == 3 ? pzr : 1] : T(0);
                     uint32_t bb[3] = {b0, b1, b2}, ll[3] = {l0, l1, l2};
-                    T wlo[3], whi[3];
-                    uint32_t lmax = 0;
+                    uint64_t* const pwin = a.cwin + static_cast<size_t>(pzr) * static_cast<size_t>(a.n);
+                    // the transfer pass takes the windows the row-sum pass
+                    // recorded when every lane's fit the packing (offset into
+                    // the row and length, 10 bits each per row, bit 63 set);
+                    // otherwise the wave searches again, to the same result
+                    bool have = false;
+                    if constexpr (TRANSFER) {
+                        const uint64_t wv = act ? (kEarly ? wkp[pzr] : pwin[i]) : (1ull << 63);
+                        have = __builtin_amdgcn_ballot_w64((wv >> 63) == 0ull) == 0ull;
+                        if (have) {
 #pragma unroll
-                    for (int q = 0; q < 3; ++q) {
-                        const T dy = dyv[q] > T(0) ? dyv[q] : T(0);
-                        const T w2 = win2_of<T>(a) - dy * dy - dz * dz;
-                        const T w = w2 > T(0) ? static_cast<T>(sqrt(w2)) + wmargin_of<T>(a) : T(0);
-                        wlo[q] = xi[0] - w;
-                        whi[q] = xi[0] + w;
-                        if (!(w2 > T(0)))
-                            ll[q] = 0;
-                        lmax = max(lmax, ll[q]);
-                    }
-                    lmax = wave_max_u32(lmax);
-                    const int nsteps = 32 - __builtin_clz(lmax | 1u);
-                    // per row, the first slot with x >= wlo and the first with
-                    // x > whi, both searched over the whole (x-sorted) row:
-                    // wlo <= whi, so the second is never before the first, and
-                    // the six searches advance together
-                    uint32_t slo[3], nlo[3], shi[3], nhi[3];
-#pragma unroll
-                    for (int q = 0; q < 3; ++q) {
-                        slo[q] = shi[q] = bb[q];
-                        nlo[q] = nhi[q] = ll[q];
-                    }
-                    for (int st = 0; st < nsteps; ++st) {
-#pragma unroll
-                        for (int q = 0; q < 3; ++q) {
-                            const uint32_t hl = nlo[q] >> 1, ml = slo[q] + hl;
-                            const uint32_t hh = nhi[q] >> 1, mh = shi[q] + hh;
-                            const bool gl = nlo[q] > 0u && lpos[0][ml < CAP ? ml : CAP - 1] < wlo[q];
-                            const bool gh = nhi[q] > 0u && !(lpos[0][mh < CAP ? mh : CAP - 1] > whi[q]);
-                            slo[q] = gl ? ml + 1u : slo[q];
-                            nlo[q] = gl ? nlo[q] - hl - 1u : hl;
-                            shi[q] = gh ? mh + 1u : shi[q];
-                            nhi[q] = gh ? nhi[q] - hh - 1u : hh;
+                            for (int q = 0; q < 3; ++q) {
+                                bb[q] += static_cast<uint32_t>(wv >> (20 * q)) & 0x3ffu;
+                                ll[q] = static_cast<uint32_t>(wv >> (20 * q + 10)) & 0x3ffu;
+                            }
                         }
                     }
+                    if (!have) {
+                        // x-window of each row from its y/z distance: |dx|^2 <= psi^2 - dy^2 - dz^2
+                        const T dz = dzv[D == 3 ? pzr : 1] > T(0) ? dzv[D == 3 ? pzr : 1] : T(0);
+                        T wlo[3], whi[3];
+                        uint32_t lmax = 0;
 #pragma unroll
-                    for (int q = 0; q < 3; ++q) {
-                        bb[q] = slo[q];
-                        ll[q] = shi[q] - slo[q];
+                        for (int q = 0; q < 3; ++q) {
+                            const T dy = dyv[q] > T(0) ? dyv[q] : T(0);
+                            const T w2 = win2_of<T>(a) - dy * dy - dz * dz;
+                            const T w = w2 > T(0) ? static_cast<T>(sqrt(w2)) + wmargin_of<T>(a) : T(0);
+                            wlo[q] = xi[0] - w;
+                            whi[q] = xi[0] + w;
+                            if (!(w2 > T(0)))
+                                ll[q] = 0;
+                            lmax = max(lmax, ll[q]);
+                        }
+                        lmax = wave_max_u32(lmax);
+                        const int nsteps = 32 - __builtin_clz(lmax | 1u);
+                        // per row, the first slot with x >= wlo and the first with
+                        // x > whi, both searched over the whole (x-sorted) row:
+                        // wlo <= whi, so the second is never before the first, and
+                        // the six searches advance together
+                        uint32_t slo[3], nlo[3], shi[3], nhi[3];
+#pragma unroll
+                        for (int q = 0; q < 3; ++q) {
+                            slo[q] = shi[q] = bb[q];
+                            nlo[q] = nhi[q] = ll[q];
+                        }
+                        for (int st = 0; st < nsteps; ++st) {
+#pragma unroll
+                            for (int q = 0; q < 3; ++q) {
+                                const uint32_t hl = nlo[q] >> 1, ml = slo[q] + hl;
+                                const uint32_t hh = nhi[q] >> 1, mh = shi[q] + hh;
+                                const bool gl = nlo[q] > 0u && lpos[0][ml < CAP ? ml : CAP - 1] < wlo[q];
+                                const bool gh = nhi[q] > 0u && !(lpos[0][mh < CAP ? mh : CAP - 1] > whi[q]);
+                                slo[q] = gl ? ml + 1u : slo[q];
+                                nlo[q] = gl ? nlo[q] - hl - 1u : hl;
+                                shi[q] = gh ? mh + 1u : shi[q];
+                                nhi[q] = gh ? nhi[q] - hh - 1u : hh;
+                            }
+                        }
+                        uint64_t pack = 1ull << 63;
+#pragma unroll
+                        for (int q = 0; q < 3; ++q) {
+                            const uint32_t off = slo[q] - bb[q];
+                            bb[q] = slo[q];
+                            ll[q] = shi[q] - slo[q];
+                            pack = (off < 1024u && ll[q] < 1024u)
+                                       ? pack | (static_cast<uint64_t>(off) << (20 * q)) |
+                                             (static_cast<uint64_t>(ll[q]) << (20 * q + 10))
+                                       : 0ull;
+                        }
+                        if constexpr (!TRANSFER) {
+                            if (act)
+                                pwin[i] = pack;
+                        }
                     }
                     b0 = bb[0]; l0 = ll[0];
                     b1 = bb[1]; l1 = ll[1];
@@ -1351,10 +1385,12 @@ __global__ __launch_bounds__(kBlock) void place_fin_k(SimArgs a, SimArgs prev)
     }
     place_body<D, typename Types<PREC>::T, typename Types<PREC>::M>(a, xcd_block(blockIdx.x - 1, gridDim.x - 1));
 }
+// The 3-d FP32W row-sum pass is held to the seven waves per SIMD that its LDS
+// allows (72 registers).
 template <int D, int PREC>
-__global__ __launch_bounds__(kBlock) void rowsum_k(SimArgs a) { tile_body<D, PREC, 1, false>(a, xcd_block(blockIdx.x, gridDim.x)); }
+__global__ __launch_bounds__(kBlock, D == 3 && PREC == 1 ? 7 : 1) void rowsum_k(SimArgs a) { tile_body<D, PREC, 1, false>(a, xcd_block(blockIdx.x, gridDim.x)); }
 template <int D, int PREC>
-__global__ __launch_bounds__(kBlock) void rowsum_kb(Batch b) { MTPT_BATCH_PROLOGUE; tile_body<D, PREC, 1, false>(a, l); }
+__global__ __launch_bounds__(kBlock, D == 3 && PREC == 1 ? 7 : 1) void rowsum_kb(Batch b) { MTPT_BATCH_PROLOGUE; tile_body<D, PREC, 1, false>(a, l); }
 
 // the 2-d FP64 one-species transfer kernel is held to the registers of 5
 // workgroups per CU, which its LDS allows

@@ -87,8 +87,8 @@ struct Plan {
     bool trim_rows = false;
     size_t tsz = 8, msz = 8;
     size_t off_x[3]{}, off_xt[3]{}, off_m[2][3]{}, off_p[2]{}, off_s = 0, off_cell = 0, off_rank = 0,
-           off_perm = 0, off_jmp[3]{}, off_cmask = 0, off_counts = 0, off_tcounts = 0, off_starts = 0, off_bsum = 0, off_part = 0, off_pair = 0,
-           off_stats = 0;
+           off_perm = 0, off_jmp[3]{}, off_cmask = 0, off_cwin = 0, off_counts = 0, off_tcounts = 0,
+           off_starts = 0, off_bsum = 0, off_part = 0, off_pair = 0, off_stats = 0;
     size_t bytes = 0;
 };
 
@@ -259,6 +259,8 @@ Plan make_plan(const mtpt_params& p)
     q.off_rank = take(n * 4);
     q.off_perm = take(n * 4);
     q.off_cmask = take(n * 8 * (q.dim == 3 ? 3 : 1));
+    if (q.trim_rows)
+        q.off_cwin = take(n * 8 * (q.dim == 3 ? 3 : 1));
     const size_t padded = static_cast<size_t>(q.scan_blocks) * kScanTile;
     q.off_counts = take(padded * 4);
     q.off_tcounts = take(padded * 4);
@@ -295,6 +297,7 @@ struct mtpt_sim {
     uint32_t *cell = nullptr, *rank = nullptr, *perm = nullptr, *counts = nullptr, *tcounts = nullptr,
              *starts = nullptr, *bsum = nullptr;
     uint64_t* cmask = nullptr;
+    uint64_t* cwin = nullptr;
     double* partials = nullptr;
     uint32_t* pair_part = nullptr;
     DevStats* st = nullptr;
@@ -339,6 +342,7 @@ void carve(mtpt_sim* s)
     s->counts = reinterpret_cast<uint32_t*>(b + q.off_counts);
     s->tcounts = reinterpret_cast<uint32_t*>(b + q.off_tcounts);
     s->cmask = reinterpret_cast<uint64_t*>(b + q.off_cmask);
+    s->cwin = q.trim_rows ? reinterpret_cast<uint64_t*>(b + q.off_cwin) : nullptr;
     s->starts = reinterpret_cast<uint32_t*>(b + q.off_starts);
     s->bsum = reinterpret_cast<uint32_t*>(b + q.off_bsum);
     s->partials = reinterpret_cast<double*>(b + q.off_part);
@@ -419,6 +423,7 @@ SimArgs base_args(const mtpt_sim* s)
     a.counts = s->counts;
     a.tcounts = s->tcounts;
     a.cmask = s->cmask;
+    a.cwin = s->cwin;
     a.starts = s->starts;
     a.bsum = s->bsum;
     a.partials = s->partials;
