@@ -30,6 +30,9 @@ def algorithmic_bytes(kernel: str, n: int, dim: int, ns: int, tsz: int, msz: int
     needs, one write of every output), per the data layout of the path."""
     pos = dim * tsz
     masks = 8 * (3 if dim == 3 else 1)             # neighbour bits per particle and plane
+    # recorded x-windows per particle and plane, where the library trims rows
+    # (rows of three cells holding 12 or more particles on average)
+    wins = masks if ncells > 0 and 3.0 * n / ncells >= 12.0 else 0
     per = {
         # x, pid in; walked x, cell, slot out
         "bin": pos + 4 + pos + 4 + 4,
@@ -37,10 +40,10 @@ def algorithmic_bytes(kernel: str, n: int, dim: int, ns: int, tsz: int, msz: int
         # perm, x, m, pid of the slot's particle in; x, m, pid and the next
         # step's jumps out
         "place": 4 + pos + ns * msz + 4 + pos + ns * msz + 4 + pos,
-        "rowsum": pos + tsz + masks,               # x in; s and masks out
-        # x, s, m, masks in; m out; then the next step's walk of the same
-        # particle: jumps in, walked x, cell, slot out
-        "transfer": pos + tsz + ns * msz + masks + ns * msz + pos + pos + 4 + 4,
+        "rowsum": pos + tsz + masks + wins,        # x in; s, masks (and windows) out
+        # x, s, m, masks (and windows) in; m out; then the next step's walk of
+        # the same particle: jumps in, walked x, cell, slot out
+        "transfer": pos + tsz + ns * msz + masks + wins + ns * msz + pos + pos + 4 + 4,
     }
     if kernel in ("scan_reduce",):
         return ncells * 8.0                        # both count arrays
