@@ -978,7 +978,7 @@ __device__ __forceinline__ void tile_body(const SimArgs& a, uint32_t blk)
                 for (int pzr = 0; pzr < planes; ++pzr)
                     mkp[pzr] = a.cmask[static_cast<size_t>(pzr) * static_cast<size_t>(a.n) + i];
             }
-            if (kEarly && use_lds && a.trim_rows && act) {
+            if (kEarly && NS == 1 && use_lds && a.trim_rows && act) {
 #pragma unroll
                 for (int pzr = 0; pzr < planes; ++pzr)
                     wkp[pzr] = a.cwin[static_cast<size_t>(pzr) * static_cast<size_t>(a.n) + i];
@@ -1014,12 +1014,14 @@ __device__ __forceinline__ void tile_body(const SimArgs& a, uint32_t blk)
                 if (a.trim_rows) {
                     uint32_t bb[3] = {b0, b1, b2}, ll[3] = {l0, l1, l2};
                     uint64_t* const pwin = a.cwin + static_cast<size_t>(pzr) * static_cast<size_t>(a.n);
-                    // the transfer pass takes the windows the row-sum pass
-                    // recorded when every lane's fit the packing (offset into
-                    // the row and length, 10 bits each per row, bit 63 set);
-                    // otherwise the wave searches again, to the same result
+                    // the one-species transfer pass takes the windows the
+                    // row-sum pass recorded when every lane's fit the packing
+                    // (offset into the row and length, 10 bits each per row,
+                    // bit 63 set); otherwise the wave searches again, to the
+                    // same result (the three-species kernels always search:
+                    // their registers are the tighter limit)
                     bool have = false;
-                    if constexpr (TRANSFER) {
+                    if constexpr (TRANSFER && NS == 1) {
                         const uint64_t wv = act ? (kEarly ? wkp[pzr] : pwin[i]) : (1ull << 63);
                         have = __builtin_amdgcn_ballot_w64((wv >> 63) == 0ull) == 0ull;
                         if (have) {
