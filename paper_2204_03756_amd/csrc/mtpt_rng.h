@@ -58,8 +58,10 @@ constexpr double inv_fact(int n)
 // fma(a, b, c) = a b + c rounded once (IEEE), with the constant addend c
 // taken from scalar registers.  Left to itself the compiler turns a fused
 // multiply-add with a constant addend into two vector moves of the constant
-// and a v_fmac; v_fma_f64 reads the scalar pair directly.  Arithmetic only:
-// the instruction's inputs are read before its result is written.
+// and a v_fmac; v_fma_f64 reads the scalar pair directly.  c must be the
+// same in every lane (here always a compile-time constant): a scalar operand
+// holds one value per wave.  Arithmetic only: the instruction's inputs are
+// read before its result is written.
 __device__ __forceinline__ double fma_sc(double a, double b, double c)
 {
     double r;
