@@ -1,15 +1,22 @@
 """Benchmark: MT pair-updates/s of the MTPT step on one MI355X.
 
-Workload: 2-d random walk + mass transfer, N = 4e6 particles uniform in
-[0,2000]^2, D_RW = D_MT = 0.5, dt = 0.1, psi = 3 sqrt(4 D_MT dt), Gaussian
-mass blob (sigma 50), 100 steps -- synthetic, seeded.  A "step" is one whole
-MTPT step (walk, binning, row sums, transfer, totals).  The FP32-weight /
-FP64-accumulation path gives ``value``; the plain FP64 path is timed beside it.
+Workload (the largest one that fits one GPU): 3-d random walk + mass
+transfer with a bimolecular A+B->C reaction after each transfer, N = 3.2e7
+particles uniform in [0,318]^3, D_RW = 0.3, D_MT = 0.7, dt = 0.05,
+psi = 3 sqrt(4 D_MT dt), three species (A = 1 for x < 159, B = 1 for
+x >= 159, C = 0), k = 1 -- synthetic, seeded.  A "step" is one whole MTPT
+step (walk, binning, row sums, transfer, reaction, totals).  The
+FP32-weight / FP64-accumulation path gives ``value``; the plain FP64 path is
+timed beside it.  A short serving mix (closed loop, then Poisson arrivals)
+is reported under ``serving``.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-fp64]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+                    [--no-cpu] [--no-fp64] [--no-serve]
 
-Prints one JSON line.  ``roofline`` is computed for the dominant kernel from
-device-side event timings of each launch and its algorithmic bytes.
+Prints one JSON line.  ``roofline`` prices the dominant kernel on its share
+of the method's algorithmic bytes (device-side event timings of each
+launch), and the whole step on the method's bytes per particle-step
+(``step_frac``).
 """
 import argparse
 import json
@@ -25,31 +32,59 @@ HBM_PEAK_GBS = 8000.0
 VALU_PEAK_GOPS = 256 * 64 * 2.4e9 / 1e9    # VALU lane-slots/s: 256 CUs x 64 lanes x 2.4 GHz
 
 
+def step_bytes(dim: int, ns: int, tsz: int, msz: int) -> float:
+    """Algorithmic HBM bytes per particle and step of the whole method, with
+    the walk fused into the transfer pass: positions p = tsz bytes per
+    coordinate, masses q = msz per species, row sums s = tsz, pid 4:
+    B = 5 d p + 4 S q + 2 s + 8 (positions read and written by the sort, read
+    by the row sums, read by the transfer and written walked; masses read and
+    written by the sort and by the transfer; row sums written and read; pid
+    read and written by the sort)."""
+    return 5.0 * dim * tsz + 4.0 * ns * msz + 2.0 * tsz + 8.0
+
+
 def algorithmic_bytes(kernel: str, n: int, dim: int, ns: int, tsz: int, msz: int, ncells: int) -> float:
-    """Bytes each launch must move at minimum (one read of every input it
-    needs, one write of every output), per the data layout of the path."""
+    """The kernel's share of the method's bytes (step_bytes), per launch:
+    place   the sort: positions, masses and pid read and written (2dp + 2Sq + 8)
+    rowsum  positions read, row sums written (dp + s)
+    transfer positions and row sums read, masses read and written, walked
+            positions written (2dp + s + 2Sq)
+    The shares add up to step_bytes; every other kernel (histogram scan,
+    scatter, finalize) and every other byte (neighbour bits, recorded
+    windows, stored jumps, cell ids and slots, halo re-reads) is overhead of
+    this implementation (overhead_bytes)."""
     pos = dim * tsz
-    masks = 8 * (3 if dim == 3 else 1)             # neighbour bits per particle and plane
+    share = {
+        "place": 2 * pos + 2 * ns * msz + 8,
+        "rowsum": pos + tsz,
+        "transfer": 2 * pos + tsz + 2 * ns * msz,
+    }
+    return float(share.get(kernel, 0) * n)
+
+
+def overhead_bytes(kernel: str, n: int, dim: int, ns: int, tsz: int, msz: int, ncells: int) -> dict:
+    """Bytes a launch moves beyond its algorithmic share, by structure (one
+    read or write each; the measured traffic adds halo re-reads and partial
+    cache lines)."""
+    planes = 3 if dim == 3 else 1
+    masks = 8 * planes                             # neighbour bits per particle and plane
     # recorded x-windows per particle and plane, where the library trims rows
     # (rows of three cells holding 12 or more particles on average)
     wins = masks if ncells > 0 and 3.0 * n / ncells >= 12.0 else 0
+    pos = dim * tsz
     per = {
-        # x, pid in; walked x, cell, slot out
-        "bin": pos + 4 + pos + 4 + 4,
-        "scatter": 4 + 4 + 4,                      # cell, rank in; perm out
-        # perm, x, m, pid of the slot's particle in; x, m, pid and the next
-        # step's jumps out
-        "place": 4 + pos + ns * msz + 4 + pos + ns * msz + 4 + pos,
-        "rowsum": pos + tsz + masks + wins,        # x in; s, masks (and windows) out
-        # x, s, m, masks (and windows) in; m out; then the next step's walk of
-        # the same particle: jumps in, walked x, cell, slot out
-        "transfer": pos + tsz + ns * msz + masks + wins + ns * msz + pos + pos + 4 + 4,
-    }
-    if kernel in ("scan_reduce",):
-        return ncells * 8.0                        # both count arrays
-    if kernel in ("scan_down",):
-        return ncells * 16.0                       # both counts in; starts out; counts cleared
-    return float(per.get(kernel, 0) * n)
+        "rowsum": {"neighbour_bits": masks, "row_windows": wins},
+        "transfer": {"neighbour_bits": masks, "row_windows": wins, "stored_jumps": pos,
+                     "cell_and_slot": 8},
+        "place": {"perm": 4, "cell_offsets": 8, "stored_jumps": pos},
+        "scatter": {"cell_and_slot": 8, "perm": 4},
+    }.get(kernel, {})
+    out = {k: float(v * n) for k, v in per.items() if v}
+    if kernel == "scan_reduce":
+        out = {"cell_counts": ncells * 8.0}
+    elif kernel == "scan_down":
+        out = {"cell_counts_and_offsets": ncells * 16.0}
+    return out
 
 
 def run_path(mt, W, precision: int, steps: int, warmup: int, profile_steps: int = 5,
@@ -124,6 +159,8 @@ def algorithmic_slots(kernel: str, n: int, pairs: int, dim: int, ns: int, prec: 
 
 
 def roofline(res, dim, ns, tsz, msz, n, prec="fp32w"):
+    """The dominant kernel against both rooflines (bound: the one with the
+    longer ideal time), plus the whole step on the method's bytes."""
     phases = res["phases"]
     if not phases:
         return None
@@ -135,9 +172,9 @@ def roofline(res, dim, ns, tsz, msz, n, prec="fp32w"):
     byt = algorithmic_bytes(name, n, dim, ns, tsz, msz, res["n_cells"])
     hbm = byt / avg_s / 1e9
     out = {**common, "bound": "hbm", "achieved": round(hbm, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-           "frac": round(hbm / HBM_PEAK_GBS, 4), "traffic": None, "bytes_per_launch": byt}
+           "frac": round(hbm / HBM_PEAK_GBS, 4), "traffic": None, "bytes_per_launch": byt,
+           "overhead_bytes_per_launch": overhead_bytes(name, n, dim, ns, tsz, msz, res["n_cells"])}
     if name in ("rowsum", "transfer"):
-        # both rooflines; the bound is the one with the longer ideal time
         slots = algorithmic_slots(name, n, res["pairs_per_step"], dim, ns, prec)
         alu = slots / avg_s / 1e9
         out["ops_per_launch"] = slots
@@ -146,6 +183,13 @@ def roofline(res, dim, ns, tsz, msz, n, prec="fp32w"):
         if alu / VALU_PEAK_GOPS > hbm / HBM_PEAK_GBS:
             out.update({"bound": "alu", "achieved": round(alu, 1), "peak": VALU_PEAK_GOPS,
                         "unit": "Gop/s", "frac": round(alu / VALU_PEAK_GOPS, 4)})
+    # the whole step: the method's bytes per particle-step over the step time
+    sb = step_bytes(dim, ns, tsz, msz) * n
+    step_s = res["ms_per_step"] / 1e3
+    out["step_bytes"] = sb
+    out["step_bytes_per_particle"] = step_bytes(dim, ns, tsz, msz)
+    out["step_achieved_gbs"] = round(sb / step_s / 1e9, 1)
+    out["step_frac"] = round(sb / step_s / 1e9 / HBM_PEAK_GBS, 4)
     return out
 
 
@@ -195,20 +239,20 @@ def profile_driver(mt, W, workload: str, precision: int, steps: int):
           flush=True)
 
 
-def cpu_baseline(W, seconds_hint: float = 20.0):
-    """The oracle on the host cores, on a bounded sample: the first steps of
-    the same 4e6-particle workload (FP32 position state, as the timed path)."""
+def cpu_baseline(W, workload: str = "react3d", steps: int = 1):
+    """The oracle on the host cores, on a bounded sample: the first step(s)
+    of the same workload (FP32 position state, as the timed path)."""
     from oracle import oracle as O
     threads = O.max_threads()
-    w = W.rw2d(precision=W.FP32W_FP64ACC)
-    steps = 5
+    w = W.make(workload, precision=W.FP32W_FP64ACC)
     t0 = time.perf_counter()
     r = O.run(w.params, w.x0, w.m0, steps, threads=threads)
     dt = time.perf_counter() - t0
     return {"value": float(r.pairs.sum()) / dt, "unit": "pair-updates/s", "cores": int(threads),
             "kind": "oracle",
-            "sample": f"first {steps} steps of the full 4e6-particle 2-d workload, "
-                      f"{int(r.pairs.sum())} pair-updates in {dt:.1f} s"}
+            "sample": f"first {steps} step(s) of the full {w.params.n:.3g}-particle {workload} workload "
+                      f"(walk, K-D tree search, transfer, reaction), {int(r.pairs.sum())} pair-updates "
+                      f"in {dt:.1f} s on {threads} threads"}
 
 
 def serve_bench(mt, W, n_req: int, seed: int = 20220404):
@@ -235,6 +279,10 @@ def serve_bench(mt, W, n_req: int, seed: int = 20220404):
     return closed, open_, rate
 
 
+SERVE_TEXT = ("serve: Poisson stream of independent 2-d/3-d sims, N log-uniform in [1e4,1e6], density 1, "
+              "D in {0.5,1,2} (D_RW = D_MT = D/2), 20-200 steps, Kahan FP32, admitted by free HBM; "
+              "closed loop first, then arrivals at 0.8x its capacity")
+
 WORKLOAD_TEXT = {
     "rw2d": "rw2d: 2-d MTPT with random walk, N=4e6 in [0,2000]^2, D_RW=D_MT=0.5, dt=0.1, "
             "psi=3*sqrt(4*D_MT*dt), 100 steps, Gaussian blob sigma 50",
@@ -244,7 +292,8 @@ WORKLOAD_TEXT = {
                "A+B->C mass-based reaction after each transfer, k=1",
     "adv2d": "adv2d: rw2d with a drift velocity v=(1, 0.5) (advection-dispersion), N=4e6 in "
              "[0,2000]^2, 100 steps",
-    "aniso2d": "aniso2d: rw2d with a diagonal dispersion tensor D_x=2D, D_y=D/2 (walk and mass "
+    "aniso2d": "aniso2d: rw2d with a rotated dispersion tensor (principal values 2D and D/2, axes at "
+               "30 degrees; walk and mass "
                "transfer), N=4e6 in [0,2000]^2, 100 steps",
 }
 
@@ -252,13 +301,17 @@ WORKLOAD_TEXT = {
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=100)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
-    ap.add_argument("--workload", default="rw2d", choices=["rw2d", "rw3d", "react3d", "adv2d", "aniso2d", "serve"],
-                    help="rw2d is the benchmark line; the others are reported the same way")
-    ap.add_argument("--requests", type=int, default=120, help="serving mix size")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--workload", default="react3d",
+                    choices=["react3d", "rw2d", "rw3d", "adv2d", "aniso2d", "serve"],
+                    help="react3d (the largest single-GPU workload) is the benchmark line; the "
+                         "others are reported the same way")
+    ap.add_argument("--requests", type=int, default=120, help="serving mix size (--workload serve)")
+    ap.add_argument("--serve-requests", type=int, default=48, help="serving mix size on the benchmark line")
     ap.add_argument("--profile-driver", action="store_true",
                     help="run a calibration copy and a few steps (for rocprofv3 --pmc)")
     ap.add_argument("--precision", default="fp32w", choices=["fp64", "fp32w", "kahan"])
@@ -284,14 +337,13 @@ def main():
             "metric": "serving mix: sims/s and p50/p99 request latency (continuous batching)",
             "value": open_["sims_per_s"], "unit": "sims/s", "n_gpus": 1,
             "higher_is_better": True, "dtype": "f32-kahan", "data": "synthetic",
-            "config": {"workload": "serve: independent 2-d/3-d sims, N log-uniform in [1e4,1e6], "
-                                   "density 1, D in {0.5,1,2}, 20-200 steps, Kahan FP32",
-                       "requests": args.requests, "poisson_rate_per_s": rate},
+            "config": {"workload": SERVE_TEXT, "requests": args.requests, "poisson_rate_per_s": rate},
             "closed_loop": closed, "poisson": open_}), flush=True)
         return
 
     workload = args.workload
     r32 = run_path(mt, W, W.FP32W_FP64ACC, args.steps, args.warmup, workload=workload)
+    print(f"fp32w path: {r32['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
     w = r32["w"]
     p = w.params
     out = {
@@ -299,9 +351,9 @@ def main():
         "value": r32["value"], "unit": "pair-updates/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": r32["ms_per_step"], "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32-weights/f64-accum",
-        "data": "synthetic (seeded uniform positions, Gaussian mass blob)",
+        "data": "synthetic (seeded uniform positions, workload's initial masses)",
         "config": {"workload": WORKLOAD_TEXT[workload],
-                   "n": p.n, "dim": p.dim, "precision": "fp32w_fp64acc",
+                   "n": p.n, "dim": p.dim, "species": p.n_species, "precision": "fp32w_fp64acc",
                    "pairs_per_step": r32["pairs_per_step"], "n_cells": r32["n_cells"]},
         "create_s_pcie_inclusive": r32["create_s"],
         "p50_step_ms": r32["p50_ms"], "p99_step_ms": r32["p99_ms"],
@@ -310,8 +362,7 @@ def main():
     ns = p.n_species
     out["roofline"] = roofline(r32, p.dim, ns, 4, 8, p.n, "fp32w")
     if out["roofline"]:
-        t = traffic_from_profile(out["roofline"]["kernel"], workload, "fp32w")
-        out["roofline"]["traffic"] = t
+        out["roofline"]["traffic"] = traffic_from_profile(out["roofline"]["kernel"], workload, "fp32w")
     if workload == "rw3d":
         rk = run_path(mt, W, W.FP32_KAHAN, args.steps, args.warmup, workload=workload)
         out["kahan_path"] = {"value": rk["value"], "ms_per_step": rk["ms_per_step"],
@@ -319,13 +370,21 @@ def main():
                              "mass_drift": rk["drift"], "roofline": roofline(rk, p.dim, ns, 4, 4, p.n, "kahan")}
     if not args.no_fp64:
         r64 = run_path(mt, W, W.FP64, args.steps, args.warmup, workload=workload)
+        print(f"fp64 path: {r64['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
+        rf = roofline(r64, p.dim, ns, 8, 8, p.n, "fp64")
+        if rf:
+            rf["traffic"] = traffic_from_profile(rf["kernel"], workload, "fp64")
         out["fp64_path"] = {"value": r64["value"], "ms_per_step": r64["ms_per_step"],
                             "p50_step_ms": r64["p50_ms"], "p99_step_ms": r64["p99_ms"],
-                            "mass_drift": r64["drift"],
-                            "roofline": roofline(r64, p.dim, ns, 8, 8, p.n, "fp64")}
+                            "mass_drift": r64["drift"], "roofline": rf}
         out["fp32_over_fp64"] = r32["value"] / r64["value"]
-    if not args.no_cpu and workload == "rw2d":
-        out["cpu_baseline"] = cpu_baseline(W)
+    if not args.no_serve:
+        closed, open_, rate = serve_bench(mt, W, args.serve_requests)
+        print(f"serving: {open_['sims_per_s']:.1f} sims/s", file=sys.stderr, flush=True)
+        out["serving"] = {"workload": SERVE_TEXT, "requests": args.serve_requests,
+                          "closed_loop": closed, "poisson": {**open_, "rate_per_s": rate}}
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(W, workload)
     print(json.dumps(out), flush=True)
 
 

@@ -42,7 +42,7 @@
 extern "C" {
 #endif
 
-#define MTPT_ABI_VERSION 3
+#define MTPT_ABI_VERSION 4
 
 typedef struct mtpt_sim mtpt_sim;   /* opaque, library-owned */
 typedef struct mtpt_pool mtpt_pool; /* opaque, library-owned */
@@ -82,20 +82,29 @@ typedef struct {
     uint64_t seed;        /* Philox key of the random walk */
     int64_t start_step;   /* index of the first step (resume), >= 0 */
     double vel[3];        /* drift velocity (advection), finite; 0 for pure dispersion */
-    double aniso[3];      /* anisotropic dispersion: D_RW and D_MT along axis k are
-                             aniso[k] times d_rw and d_mt (all > 0), or all 0 for
-                             isotropic dispersion; see the note below */
+    double disp[9];       /* shape tensor T of the dispersion, row-major [3][3]: D_RW = d_rw T,
+                             D_MT = d_mt T; all zero for isotropic dispersion (T = I).
+                             See the note below. */
 } mtpt_params;
 
-/* Anisotropic dispersion (a diagonal dispersion tensor in the kernel of
- * Sec. 3): the walk and the mass transfer share the tensor diag(aniso),
- * scaled by d_rw and d_mt respectively.  The step is then isotropic in the
- * frame x'_k = x_k c_k with c_k = 1/sqrt(aniso_k), where the library runs it:
- * box and vel are scaled alike, positions are multiplied by c_k in FP64 at
- * create (then rounded once to the position type) and divided by c_k in
- * FP64 by mtpt_positions.  psi and the neighbour sets of mtpt_neighbors are
- * those of the scaled frame; in the caller's frame the cutoff is the
- * ellipsoid sum_k dx_k^2 / aniso_k <= psi^2. */
+/* Dispersion tensor (Sec. 2: the advection-dispersion equation carries a
+ * dispersion tensor D; Sec. 3, Eq. (2): the mass-transfer kernel written with
+ * the tensor D_MT; the paper's runs take D = D I).  T must be symmetric and
+ * positive definite in its leading dim x dim block (the rest is ignored).
+ * With T = L L^T (Cholesky) and M = L^-1, everything runs in the caller's
+ * frame and box:
+ *   - jumps: X += v dt + sqrt(2 d_rw dt) L xi (covariance 2 dt D_RW);
+ *   - kernel: K = exp(-beta q / (4 d_mt dt)) with the Mahalanobis distance
+ *     q = dx^T T^-1 dx = |M dx|^2 (Eq. (2) prints D_MT in the exponent; its
+ *     inverse is the dimensionally consistent reading);
+ *   - cutoff: q <= psi^2, an ellipsoid, found through cells of side at least
+ *     psi sqrt(T_kk) along axis k;
+ *   - walls: the box's faces, mirrors as in the isotropic case.
+ * L, M and q are formed in one fixed order (L00 = sqrt(T00), L10 = T10/L00,
+ * L11 = sqrt(T11 - L10 L10), L20 = T20/L00, L21 = (T21 - L20 L10)/L11,
+ * L22 = sqrt((T22 - L20 L20) - L21 L21); M by forward substitution;
+ * y = M dx row by row in ascending column order, q = (y0 y0 + y1 y1) + y2 y2),
+ * and with T = I they reduce to the isotropic forms bit for bit. */
 
 typedef struct {
     void* (*alloc)(size_t bytes, void* ctx); /* returns device memory or NULL */
@@ -146,6 +155,19 @@ int mtpt_stats(mtpt_sim* sim, mtpt_stats_t* out);
  * row_ptr[n+1] (always written), col[nnz] written only when nnz <= cap.
  * *nnz_out receives nnz.  Synchronises.  A debug/test export, not a step. */
 int mtpt_neighbors(mtpt_sim* sim, int64_t* row_ptr, int64_t* col, int64_t cap, int64_t* nnz_out);
+
+/* Neighbour sets exactly as a hot pass of the last step used them, in the
+ * CSR format of mtpt_neighbors (pid order, rows ascending, self included):
+ * which = 0: the row-sum pass (every candidate it found within the cutoff,
+ * Sec. 3 Eq. (1), the sums s_i of the normalisation run over these);
+ * which = 1: the transfer pass (every pair whose weight it applied, Eq. (5):
+ * the neighbour bits the row-sum pass recorded, decoded over the same
+ * (trimmed) candidate rows, or its own candidate loop where a wave has no
+ * bits).  Re-runs that pass on the last step's state without storing
+ * anything.  MTPT_E_STATE before the first step; MTPT_E_ARG for another
+ * which.  Synchronises.  A debug/test export, not a step. */
+int mtpt_step_neighbors(mtpt_sim* sim, int32_t which, int64_t* row_ptr, int64_t* col, int64_t cap,
+                        int64_t* nnz_out);
 
 /* Free the sim's device memory (and stream, if library-owned).  NULL is a
  * no-op.  Synchronises on the sim's stream first. */

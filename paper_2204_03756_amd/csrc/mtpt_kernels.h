@@ -118,7 +118,8 @@ struct SimArgs {
     int64_t n;
     int32_t ns;              // species (1 or 3)
     int32_t moving;          // particles move (D_RW > 0 or a drift)
-    // cell grid: cell side >= psi in every dimension
+    // cell grid: cell side >= the cutoff's reach along every axis (psi, or
+    // psi sqrt(T_kk) with a dispersion tensor)
     double glo[3];
     double inv_side[3];
     int32_t nc[3];
@@ -183,6 +184,17 @@ struct SimArgs {
     int32_t tcounts_valid;   // this step's binning came from the transfer pass:
                              // cell count = counts + tcounts
     int32_t trim_rows;       // trim candidate rows to the per-row x-window
+    // dispersion tensor T = L L^T (shape of D_RW and D_MT): jumps L z, distance
+    // q = |M dx|^2 with M = L^-1 (tensor == 0: isotropic, L = M = I unused)
+    int32_t tensor;
+    int32_t pad4;
+    double lch[6];           // L00, L10, L11, L20, L21, L22
+    double minv[6];          // M00, M10, M11, M20, M21, M22
+    float minvf[6];          // M rounded to FP32
+    // export of the pairs a tiled pass uses (mtpt_step_neighbors; null otherwise)
+    uint32_t* nb_cnt;        // count pass: pairs + 1 per pid
+    const int64_t* nb_row;   // fill pass: CSR row offsets by pid
+    int64_t* nb_col;         // fill pass: CSR columns (pids)
 };
 
 // Batched launches: a device array of SimArgs and a device prefix of blocks
@@ -221,8 +233,17 @@ hipError_t launch_phase(int ph, int dim, int prec, const SimArgs& a, hipStream_t
 // PH_PLACE of a, with the PH_FINALIZE of the previous step prev run by one
 // more workgroup of the same launch
 hipError_t launch_place_fin(int dim, int prec, const SimArgs& a, const SimArgs& prev, hipStream_t s);
-// batched launch of a phase over sims that share (dim, prec, ns)
-hipError_t launch_phase_batched(int ph, int dim, int prec, int ns, const Batch& b, hipStream_t s);
+// batched launch of a phase over sims that share (dim, prec, ns, tensor)
+hipError_t launch_phase_batched(int ph, int dim, int prec, int ns, int tn, const Batch& b, hipStream_t s);
+// the two tiled passes (PH_ROWSUM, PH_TRANSFER) of dimension D, isotropic or
+// tensor metric TN: one sim (a) or a batch (b, with a == nullptr)
+template <int D, bool TN>
+hipError_t launch_tiles(int ph, int prec, int ns, const SimArgs* a, const Batch* b, hipStream_t s);
+// the same passes recording the pairs they use (a.nb_* set), storing nothing
+template <int D, bool TN>
+hipError_t launch_tiles_export(int ph, int prec, int ns, const SimArgs& a, hipStream_t s);
+// rows of a CSR sorted ascending, in place
+hipError_t launch_nb_sort(int64_t n, const int64_t* row_ptr, int64_t* col, hipStream_t s);
 
 // exports and set-up
 hipError_t launch_unpermute_mass(int prec, const SimArgs& a, const void* const* m_cur,

@@ -85,12 +85,98 @@ struct Plan {
     int tile[3] = {1, 1, 1};
     uint32_t tiles_x = 1, tiles_y = 1, ntiles = 0;
     bool trim_rows = false;
+    bool tensor = false;
     size_t tsz = 8, msz = 8;
     size_t off_x[3]{}, off_xt[3]{}, off_m[2][3]{}, off_p[2]{}, off_s = 0, off_cell = 0, off_rank = 0,
            off_perm = 0, off_jmp[3]{}, off_cmask = 0, off_cwin = 0, off_counts = 0, off_tcounts = 0,
            off_starts = 0, off_bsum = 0, off_part = 0, off_pair = 0, off_stats = 0;
     size_t bytes = 0;
 };
+
+// Shape tensor T of the dispersion (D_RW = d_rw T, D_MT = d_mt T), its
+// Cholesky factor L and M = L^-1, each entry formed in the fixed order of
+// the C-ABI's note: L00 = sqrt(T00), L10 = T10 / L00, L11 = sqrt(T11 - L10 L10),
+// L20 = T20 / L00, L21 = (T21 - L20 L10) / L11, L22 = sqrt((T22 - L20 L20) - L21 L21);
+// M00 = 1/L00, M11 = 1/L11, M22 = 1/L22, M10 = -((L10 M00) M11),
+// M21 = -((L21 M11) M22), M20 = -(((L20 M00) + (L21 M10)) M22).
+struct Tensor {
+    bool on = false;          // false: isotropic (T = I)
+    double t[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1};
+    double l[6] = {1, 0, 1, 0, 0, 1};
+    double m[6] = {1, 0, 1, 0, 0, 1};
+    double cond = 9.0;        // trace(T^-1) trace(T), the FP32 error factor of q
+};
+
+// 0, or -1 with a message in *why when T is not a symmetric positive-definite
+// tensor (all zero is the isotropic default)
+int tensor_of(const mtpt_params& p, Tensor* out, const char** why)
+{
+#pragma clang fp contract(off)
+    Tensor g;
+    const int d = p.dim;
+    bool any = false;
+    for (int k = 0; k < 9; ++k) {
+        if (!std::isfinite(p.disp[k])) {
+            *why = "disp must be finite";
+            return -1;
+        }
+        const int r = k / 3, c = k % 3;
+        if (r < d && c < d)
+            any = any || p.disp[k] != 0.0;
+    }
+    if (!any) {
+        g.cond = static_cast<double>(d * d);
+        *out = g;
+        return 0;
+    }
+    for (int r = 0; r < d; ++r)
+        for (int c = 0; c < d; ++c)
+            if (p.disp[r * 3 + c] != p.disp[c * 3 + r]) {
+                *why = "disp must be symmetric";
+                return -1;
+            }
+    g.on = true;
+    for (int k = 0; k < 9; ++k)
+        g.t[k] = (k / 3 < d && k % 3 < d) ? p.disp[k] : (k / 3 == k % 3 ? 1.0 : 0.0);
+    const double* t = g.t;
+    double* l = g.l;
+    double* m = g.m;
+    *why = "disp must be positive definite";
+    if (!(t[0] > 0.0))
+        return -1;
+    l[0] = std::sqrt(t[0]);
+    l[1] = t[3] / l[0];
+    const double p1 = t[4] - l[1] * l[1];
+    if (!(p1 > 0.0))
+        return -1;
+    l[2] = std::sqrt(p1);
+    m[0] = 1.0 / l[0];
+    m[2] = 1.0 / l[2];
+    m[1] = -((l[1] * m[0]) * m[2]);
+    l[3] = l[4] = m[3] = m[4] = 0.0;
+    l[5] = m[5] = 1.0;
+    if (d == 3) {
+        l[3] = t[6] / l[0];
+        l[4] = (t[7] - l[3] * l[1]) / l[2];
+        const double p2 = (t[8] - l[3] * l[3]) - l[4] * l[4];
+        if (!(p2 > 0.0))
+            return -1;
+        l[5] = std::sqrt(p2);
+        m[5] = 1.0 / l[5];
+        m[4] = -((l[4] * m[2]) * m[5]);
+        m[3] = -(((l[3] * m[0]) + (l[4] * m[1])) * m[5]);
+    }
+    // trace(T^-1) = |M|_F^2 (T^-1 = M^T M) times trace(T)
+    double fro = 0.0, tr = 0.0;
+    for (int k = 0; k < 6; ++k)
+        fro += (k == 3 || k == 4 || k == 5) && d == 2 ? 0.0 : m[k] * m[k];
+    for (int k = 0; k < d; ++k)
+        tr += t[k * 3 + k];
+    g.cond = fro * tr;
+    *why = "";
+    *out = g;
+    return 0;
+}
 
 int validate(const mtpt_params* p)
 {
@@ -115,14 +201,10 @@ int validate(const mtpt_params* p)
         if (!std::isfinite(p->vel[k]))
             return fail(MTPT_E_ARG, "vel must be finite");
     {
-        int zero = 0;
-        for (int k = 0; k < p->dim; ++k) {
-            if (!std::isfinite(p->aniso[k]) || p->aniso[k] < 0)
-                return fail(MTPT_E_ARG, "aniso must be finite and >= 0");
-            zero += p->aniso[k] == 0.0;
-        }
-        if (zero != 0 && zero != p->dim)
-            return fail(MTPT_E_ARG, "aniso: all components > 0, or all 0 (isotropic)");
+        Tensor g;
+        const char* why = "";
+        if (tensor_of(*p, &g, &why) != 0)
+            return fail(MTPT_E_ARG, "%s", why);
     }
     if (!std::isfinite(p->d_mt) || !(p->d_mt > 0))
         return fail(MTPT_E_ARG, "d_mt must be finite and > 0");
@@ -151,11 +233,17 @@ Plan make_plan(const mtpt_params& p)
     q.psi = psi_of(p);
     q.tsz = p.precision == MTPT_FP64 ? 8 : 4;
     q.msz = p.precision == MTPT_FP32_KAHAN ? 4 : 8;
-    // cells of side >= psi (1 + 1e-6): every pair within psi then lies in
+    // cells of side >= psi (1 + 1e-6) along every axis -- psi sqrt(T_kk)
+    // (1 + 1e-6), the reach of the ellipsoid q <= psi^2 along axis k, with a
+    // dispersion tensor: every pair within the cutoff then lies in
     // neighbouring cells even after rounding of the cell coordinate
-    double side_min = q.psi * (1.0 + 1e-6);
+    Tensor g;
+    const char* why = "";
+    (void)tensor_of(p, &g, &why);
+    q.tensor = g.on;
     for (int k = 0; k < q.dim; ++k) {
         const double L = p.hi[k] - p.lo[k];
+        const double side_min = q.psi * std::sqrt(g.t[k * 3 + k]) * (1.0 + 1e-6);
         double c = std::floor(L / side_min);
         c = std::min(std::max(c, 1.0), 1048576.0);
         q.nc[k] = static_cast<int>(c);
@@ -234,7 +322,7 @@ Plan make_plan(const mtpt_params& p)
         q.ntiles = q.tiles_x * q.tiles_y * static_cast<uint32_t>(q.dim == 3 ? (q.nc[2] + tz - 1) / tz : 1);
         // rows of three cells long enough that trimming them to the x-window
         // saves more candidates than its two binary searches cost
-        q.trim_rows = 3.0 * rho_c >= MTPT_TRIM_MIN_ROW;
+        q.trim_rows = !q.tensor && 3.0 * rho_c >= MTPT_TRIM_MIN_ROW;
     }
     const size_t n = static_cast<size_t>(q.n);
     size_t off = 0;
@@ -281,8 +369,8 @@ struct PhaseEv {
 }  // namespace
 
 struct mtpt_sim {
-    mtpt_params p{};          // the parameters in the scaled frame (box, drift)
-    double scale[3] = {1.0, 1.0, 1.0};   // x' = x scale_k (anisotropic dispersion)
+    mtpt_params p{};
+    Tensor tens;              // dispersion tensor (isotropic: tens.on == false)
     Plan q;
     Alloc alloc;
     hipStream_t stream = nullptr;
@@ -382,7 +470,7 @@ SimArgs base_args(const mtpt_sim* s)
     a.seed = p.seed;
     a.psi = q.psi;
     a.psi2 = q.psi * q.psi;
-    a.win = q.psi * (1.0 + 1e-6);
+    a.win = q.psi * std::sqrt(s->tens.t[0]) * (1.0 + 1e-6);
     a.win2d = a.win * a.win;
     a.win2f = static_cast<float>(a.win2d);
     {
@@ -397,8 +485,19 @@ SimArgs base_args(const mtpt_sim* s)
     }
     for (int k = 0; k < 3; ++k)
         a.side[k] = q.inv_side[k] > 0.0 ? 1.0 / q.inv_side[k] : 0.0;
-    a.psi2_in = static_cast<float>(a.psi2 * (1.0 - 1e-5));
-    a.psi2_out = static_cast<float>(a.psi2 * (1.0 + 1e-5));
+    // relative band of the FP32 cutoff test: the isotropic FP32 r^2 is within
+    // 1e-6 of the FP64 one; the FP32 Mahalanobis form within
+    // (10 sqrt(cond) + 3) 2^-24, cond = trace(T^-1) trace(T), with a factor 4 of margin
+    const double band = s->tens.on ? std::max(1e-5, 4.0 * (10.0 * std::sqrt(s->tens.cond) + 3.0) * 5.960464477539063e-08)
+                                   : 1e-5;
+    a.psi2_in = static_cast<float>(a.psi2 * (1.0 - band));
+    a.psi2_out = static_cast<float>(a.psi2 * (1.0 + band));
+    a.tensor = s->tens.on ? 1 : 0;
+    for (int k = 0; k < 6; ++k) {
+        a.lch[k] = s->tens.l[k];
+        a.minv[k] = s->tens.m[k];
+        a.minvf[k] = static_cast<float>(s->tens.m[k]);
+    }
     a.kc = p.beta / (4.0 * p.d_mt * p.dt);
     a.kcf = static_cast<float>(a.kc);
     a.kcf2 = static_cast<float>(-a.kc * 1.4426950408889634);
@@ -612,17 +711,15 @@ int create_into(mtpt_sim* s, const double* pos, const double* mass)
     if (n > 0) {
         std::vector<unsigned char> stage(std::max(n * q.tsz, n * q.msz));
         for (int k = 0; k < q.dim; ++k) {
-            // the scaled frame x' = x scale_k in FP64, rounded once to the
-            // position type
-            const double sc = s->scale[k];
+            // coordinate k, rounded once to the position type
             if (q.tsz == 8) {
                 double* d = reinterpret_cast<double*>(stage.data());
                 for (size_t i = 0; i < n; ++i)
-                    d[i] = pos[i * q.dim + k] * sc;
+                    d[i] = pos[i * q.dim + k];
             } else {
                 float* f = reinterpret_cast<float*>(stage.data());
                 for (size_t i = 0; i < n; ++i)
-                    f[i] = static_cast<float>(pos[i * q.dim + k] * sc);
+                    f[i] = static_cast<float>(pos[i * q.dim + k]);
             }
             HIP_TRY(hipMemcpy(s->X[k], stage.data(), n * q.tsz, hipMemcpyHostToDevice));
         }
@@ -698,15 +795,10 @@ int new_sim(const mtpt_params* params, const double* pos, const double* mass, vo
     if (alloc && (!alloc->alloc || !alloc->free))
         return fail(MTPT_E_ARG, "allocator needs both alloc and free");
     mtpt_sim* s = new mtpt_sim();
-    // anisotropic dispersion D_k = aniso_k D: the step is isotropic in the
-    // frame x'_k = x_k / sqrt(aniso_k), where box and drift are scaled too
     s->p = *params;
-    for (int k = 0; k < params->dim; ++k) {
-        if (params->aniso[k] > 0.0)
-            s->scale[k] = 1.0 / std::sqrt(params->aniso[k]);
-        s->p.lo[k] = params->lo[k] * s->scale[k];
-        s->p.hi[k] = params->hi[k] * s->scale[k];
-        s->p.vel[k] = params->vel[k] * s->scale[k];
+    {
+        const char* why = "";
+        (void)tensor_of(s->p, &s->tens, &why);   // validated above
     }
     s->q = make_plan(s->p);
     s->moving = s->p.d_rw > 0.0;
@@ -841,12 +933,6 @@ int mtpt_positions(mtpt_sim* s, double* out)
     s->alloc.put(d);
     if (e != hipSuccess)
         return fail(MTPT_E_DEVICE, "mtpt_positions: %s", hipGetErrorString(e));
-    // back from the scaled frame: x = x' / scale_k (FP64)
-    const int dim = s->q.dim;
-    for (int k = 0; k < dim; ++k)
-        if (s->scale[k] != 1.0)
-            for (size_t i = 0; i < n; ++i)
-                out[i * dim + k] = out[i * dim + k] / s->scale[k];
     return MTPT_OK;
 }
 
@@ -888,15 +974,18 @@ int mtpt_stats(mtpt_sim* s, mtpt_stats_t* out)
     return MTPT_OK;
 }
 
-int mtpt_neighbors(mtpt_sim* s, int64_t* row_ptr, int64_t* col, int64_t cap, int64_t* nnz_out)
+}  // extern "C"
+
+namespace {
+
+// CSR export in pid order: count(rowcnt) fills rowcnt[pid] with each row's
+// length, fill(row_ptr, col) writes the rows (sorted ascending) from device
+// row offsets.  Scratch comes from the sim's allocator.
+template <typename Count, typename Fill>
+int csr_export(mtpt_sim* s, int64_t* row_ptr, int64_t* col, int64_t cap, int64_t* nnz_out, Count count,
+               Fill fill)
 {
-    if (!s || !row_ptr || !nnz_out)
-        return fail(MTPT_E_ARG, "NULL argument");
     const int64_t n = s->q.n;
-    row_ptr[0] = 0;
-    *nnz_out = 0;
-    if (n == 0)
-        return MTPT_OK;
     const int64_t tiles = (n + 1 + kScanTile - 1) / kScanTile;
     uint32_t* rowcnt = static_cast<uint32_t*>(s->alloc.get(static_cast<size_t>(n) * 4));
     uint32_t* tmp = static_cast<uint32_t*>(s->alloc.get(static_cast<size_t>(tiles) * kScanTile * 4));
@@ -910,8 +999,7 @@ int mtpt_neighbors(mtpt_sim* s, int64_t* row_ptr, int64_t* col, int64_t cap, int
         goto done;
     }
     {
-        SimArgs a = base_args(s);
-        e = launch_nb_count(s->q.dim, s->q.prec, a, cur_pid(s), rowcnt, s->stream);
+        e = count(rowcnt);
         if (e == hipSuccess)
             e = launch_scan_u32_to_i64(rowcnt, drp, n, tmp, bs, s->stream);
         if (e == hipSuccess)
@@ -919,7 +1007,7 @@ int mtpt_neighbors(mtpt_sim* s, int64_t* row_ptr, int64_t* col, int64_t cap, int
         if (e == hipSuccess)
             e = hipStreamSynchronize(s->stream);
         if (e != hipSuccess) {
-            rc = fail(MTPT_E_DEVICE, "mtpt_neighbors: %s", hipGetErrorString(e));
+            rc = fail(MTPT_E_DEVICE, "neighbour export: %s", hipGetErrorString(e));
             goto done;
         }
         const int64_t nnz = row_ptr[n];
@@ -930,13 +1018,13 @@ int mtpt_neighbors(mtpt_sim* s, int64_t* row_ptr, int64_t* col, int64_t cap, int
                 rc = fail(MTPT_E_NOMEM, "neighbour export allocation failed");
                 goto done;
             }
-            e = launch_nb_fill(s->q.dim, s->q.prec, a, cur_pid(s), drp, dcol, s->stream);
+            e = fill(drp, dcol);
             if (e == hipSuccess)
                 e = hipMemcpyAsync(col, dcol, static_cast<size_t>(nnz) * 8, hipMemcpyDeviceToHost, s->stream);
             if (e == hipSuccess)
                 e = hipStreamSynchronize(s->stream);
             if (e != hipSuccess)
-                rc = fail(MTPT_E_DEVICE, "mtpt_neighbors: %s", hipGetErrorString(e));
+                rc = fail(MTPT_E_DEVICE, "neighbour export: %s", hipGetErrorString(e));
         }
     }
 done:
@@ -947,6 +1035,74 @@ done:
     s->alloc.put(drp);
     s->alloc.put(dcol);
     return rc;
+}
+
+hipError_t export_pass(const mtpt_sim* s, int ph, const SimArgs& a)
+{
+    const int prec = s->q.prec, ns = s->q.ns;
+    if (s->q.dim == 2)
+        return s->tens.on ? launch_tiles_export<2, true>(ph, prec, ns, a, s->stream)
+                          : launch_tiles_export<2, false>(ph, prec, ns, a, s->stream);
+    return s->tens.on ? launch_tiles_export<3, true>(ph, prec, ns, a, s->stream)
+                      : launch_tiles_export<3, false>(ph, prec, ns, a, s->stream);
+}
+
+}  // namespace
+
+extern "C" {
+
+int mtpt_neighbors(mtpt_sim* s, int64_t* row_ptr, int64_t* col, int64_t cap, int64_t* nnz_out)
+{
+    if (!s || !row_ptr || !nnz_out)
+        return fail(MTPT_E_ARG, "NULL argument");
+    row_ptr[0] = 0;
+    *nnz_out = 0;
+    if (s->q.n == 0)
+        return MTPT_OK;
+    const SimArgs a = base_args(s);
+    const int dim = s->q.dim, prec = s->q.prec;
+    const uint32_t* pid = cur_pid(s);
+    return csr_export(
+        s, row_ptr, col, cap, nnz_out,
+        [&](uint32_t* rowcnt) { return launch_nb_count(dim, prec, a, pid, rowcnt, s->stream); },
+        [&](const int64_t* drp, int64_t* dcol) { return launch_nb_fill(dim, prec, a, pid, drp, dcol, s->stream); });
+}
+
+int mtpt_step_neighbors(mtpt_sim* s, int32_t which, int64_t* row_ptr, int64_t* col, int64_t cap,
+                        int64_t* nnz_out)
+{
+    if (!s || !row_ptr || !nnz_out)
+        return fail(MTPT_E_ARG, "NULL argument");
+    if (which != 0 && which != 1)
+        return fail(MTPT_E_ARG, "which must be 0 (row-sum pass) or 1 (transfer pass)");
+    row_ptr[0] = 0;
+    *nnz_out = 0;
+    if (s->q.n == 0)
+        return MTPT_OK;
+    if (s->steps_done == 0)
+        return fail(MTPT_E_STATE, "no step has run yet");
+    // the last step's arguments: its sorted positions, cell offsets, row
+    // sums, neighbour bits and windows are still in place until the next step
+    SimArgs a = s->fin_args;
+    const int ph = which == 0 ? PH_ROWSUM : PH_TRANSFER;
+    const int64_t n = s->q.n;
+    return csr_export(
+        s, row_ptr, col, cap, nnz_out,
+        [&](uint32_t* rowcnt) {
+            a.nb_cnt = rowcnt;
+            a.nb_row = nullptr;
+            a.nb_col = nullptr;
+            return export_pass(s, ph, a);
+        },
+        [&](const int64_t* drp, int64_t* dcol) {
+            a.nb_cnt = nullptr;
+            a.nb_row = drp;
+            a.nb_col = dcol;
+            hipError_t e = export_pass(s, ph, a);
+            if (e == hipSuccess)
+                e = launch_nb_sort(n, drp, dcol, s->stream);
+            return e;
+        });
 }
 
 int mtpt_destroy(mtpt_sim* s)
@@ -1061,10 +1217,11 @@ int ring_reserve(mtpt_pool* p, RingSlot& r, size_t bytes)
 }
 
 struct GroupKey {
-    int dim, prec, ns, moving, rowsum, bin;
+    int dim, prec, ns, tensor, moving, rowsum, bin;
     bool operator<(const GroupKey& o) const
     {
         if (dim != o.dim) return dim < o.dim;
+        if (tensor != o.tensor) return tensor < o.tensor;
         if (prec != o.prec) return prec < o.prec;
         if (ns != o.ns) return ns < o.ns;
         if (moving != o.moving) return moving < o.moving;
@@ -1154,7 +1311,7 @@ int mtpt_pool_tick(mtpt_pool* p, int32_t* n_completed)
         mtpt_sim* s = kv.second;
         if (s->steps_done >= s->steps_target || s->q.n == 0)
             continue;
-        const GroupKey k{s->q.dim, s->q.prec, s->q.ns, s->moving ? 1 : 0, (s->moving || !s->s_valid) ? 1 : 0,
+        const GroupKey k{s->q.dim, s->q.prec, s->q.ns, s->tens.on ? 1 : 0, s->moving ? 1 : 0, (s->moving || !s->s_valid) ? 1 : 0,
                          (s->moving && !s->bin_ready) ? 1 : 0};
         groups[k].push_back(s);
     }
@@ -1222,7 +1379,7 @@ int mtpt_pool_tick(mtpt_pool* p, int32_t* n_completed)
                 b.blk_off = dpre + ph * (ns + 1);
                 b.nsims = static_cast<int32_t>(ns);
                 b.total_blocks = hpre[ph * (ns + 1) + ns];
-                HIP_TRY(launch_phase_batched(ph, k.dim, k.prec, k.ns, b, p->stream));
+                HIP_TRY(launch_phase_batched(ph, k.dim, k.prec, k.ns, k.tensor, b, p->stream));
             }
             for (mtpt_sim* s : g.second) {
                 s->steps_done += 1;

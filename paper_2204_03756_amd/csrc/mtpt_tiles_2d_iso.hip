@@ -1,0 +1,10 @@
+// mtpt_tiles_2d_iso.hip -- the row-sum and transfer passes of the MTPT step for 2-d
+// simulations with isotropic dispersion, single and batched
+// launches (one translation unit per dimension and metric, so that the
+// build compiles them in parallel).
+#include "mtpt_device.h"
+
+namespace mtpt {
+template hipError_t launch_tiles<2, false>(int, int, int, const SimArgs*, const Batch*, hipStream_t);
+template hipError_t launch_tiles_export<2, false>(int, int, int, const SimArgs&, hipStream_t);
+}  // namespace mtpt

@@ -17,7 +17,7 @@ import numpy as np
 
 from . import build as _build
 
-MTPT_ABI_VERSION = 3
+MTPT_ABI_VERSION = 4
 MTPT_OK, MTPT_E_ARG, MTPT_E_NOMEM, MTPT_E_DEVICE, MTPT_E_NONFINITE, MTPT_E_ABI, MTPT_E_STATE = \
     0, -1, -2, -3, -4, -5, -6
 MTPT_FP64, MTPT_FP32W_FP64ACC, MTPT_FP32_KAHAN = 0, 1, 2
@@ -37,7 +37,7 @@ class mtpt_params(C.Structure):
         ("d_rw", C.c_double), ("d_mt", C.c_double), ("dt", C.c_double), ("beta", C.c_double),
         ("psi", C.c_double), ("k_react", C.c_double),
         ("seed", C.c_uint64), ("start_step", C.c_int64),
-        ("vel", C.c_double * 3), ("aniso", C.c_double * 3),
+        ("vel", C.c_double * 3), ("disp", C.c_double * 9),
     ]
 
 
@@ -86,6 +86,7 @@ def load():
         "mtpt_positions": (C.c_int, [C.c_void_p, _f64p]),
         "mtpt_stats": (C.c_int, [C.c_void_p, P(mtpt_stats_t)]),
         "mtpt_neighbors": (C.c_int, [C.c_void_p, _i64p, _i64p, C.c_int64, _i64p]),
+        "mtpt_step_neighbors": (C.c_int, [C.c_void_p, C.c_int32, _i64p, _i64p, C.c_int64, _i64p]),
         "mtpt_destroy": (C.c_int, [C.c_void_p]),
         "mtpt_last_error": (C.c_char_p, []),
         "mtpt_abi_version": (C.c_int, []),
@@ -140,9 +141,14 @@ def make_params(p) -> mtpt_params:
     vel = getattr(p, "vel", None) or (0.0, 0.0, 0.0)
     for k in range(3):
         q.vel[k] = float(vel[k]) if k < len(vel) else 0.0
-    aniso = getattr(p, "aniso", None) or (0.0, 0.0, 0.0)
-    for k in range(3):
-        q.aniso[k] = float(aniso[k]) if k < len(aniso) else 0.0
+    disp = getattr(p, "disp", None) or [0.0] * 9
+    disp = [float(v) for v in np.asarray(disp, dtype=np.float64).reshape(-1)]
+    if len(disp) == 4:                       # a 2-d tensor: embed in 3x3
+        disp = [disp[0], disp[1], 0.0, disp[2], disp[3], 0.0, 0.0, 0.0, 1.0]
+    if len(disp) != 9:
+        raise ValueError("disp must hold 9 (or 4) values")
+    for k in range(9):
+        q.disp[k] = disp[k]
     return q
 
 
@@ -238,6 +244,19 @@ def mtpt_neighbors(sim, n: int):
     col = np.zeros(max(nnz.value, 1), dtype=np.int64)
     _check(lib.mtpt_neighbors(sim, row.ctypes.data_as(_i64p), col.ctypes.data_as(_i64p),
                               nnz.value, C.byref(nnz)))
+    return row, col[:nnz.value]
+
+
+def mtpt_step_neighbors(sim, n: int, which: int):
+    """Pairs the row-sum (which=0) or transfer (which=1) pass of the last step
+    used, as CSR in pid order (self included)."""
+    lib = load()
+    row = np.zeros(n + 1, dtype=np.int64)
+    nnz = C.c_int64()
+    _check(lib.mtpt_step_neighbors(sim, int(which), row.ctypes.data_as(_i64p), None, 0, C.byref(nnz)))
+    col = np.zeros(max(nnz.value, 1), dtype=np.int64)
+    _check(lib.mtpt_step_neighbors(sim, int(which), row.ctypes.data_as(_i64p), col.ctypes.data_as(_i64p),
+                                   nnz.value, C.byref(nnz)))
     return row, col[:nnz.value]
 
 
@@ -350,6 +369,10 @@ class Sim:
 
     def neighbors(self):
         return mtpt_neighbors(self.h, self.n)
+
+    def step_neighbors(self, which: int):
+        """The pairs the last step's row-sum (0) or transfer (1) pass used."""
+        return mtpt_step_neighbors(self.h, self.n, which)
 
     def close(self):
         if self.h:

@@ -53,7 +53,9 @@ class Params:
     start_step: int = 0
     precision: int = FP64
     vel: List[float] = field(default_factory=lambda: [0.0, 0.0, 0.0])   # drift velocity
-    aniso: List[float] = field(default_factory=lambda: [0.0, 0.0, 0.0])  # D_k / D (0: isotropic)
+    # shape tensor T of the dispersion, row-major [3][3]: D_RW = d_rw T and
+    # D_MT = d_mt T (all zero: isotropic, T = I)
+    disp: List[float] = field(default_factory=lambda: [0.0] * 9)
 
     @property
     def psi_eff(self) -> float:
@@ -72,7 +74,7 @@ class Params:
             "d_rw": self.d_rw, "d_mt": self.d_mt, "dt": self.dt, "beta": self.beta,
             "psi": self.psi, "k_react": self.k_react, "n_species": self.n_species,
             "seed": self.seed, "start_step": self.start_step, "precision": self.precision,
-            "vel": list(self.vel), "aniso": list(self.aniso),
+            "vel": list(self.vel), "disp": list(self.disp),
         }
 
 
@@ -156,12 +158,39 @@ def adv2d(n: int = 4_000_000, steps: int = 100, precision: int = FP32W_FP64ACC) 
     return Workload("adv2d", p, w.x0, w.m0, steps, {**w.notes, "vel": [1.0, 0.5]})
 
 
+def diag_tensor(a) -> List[float]:
+    """Row-major [3][3] shape tensor diag(a) (unused diagonal entries 1)."""
+    t = np.eye(3)
+    for k, v in enumerate(a):
+        t[k, k] = float(v)
+    return t.reshape(-1).tolist()
+
+
+def rotated_tensor(eigs, angles) -> List[float]:
+    """Row-major [3][3] shape tensor R diag(eigs) R^T, R the rotation by the
+    given angles (radians) about z, then y, then x; a 2-d tensor takes two
+    eigenvalues and one angle (about z)."""
+    e = list(eigs) + [1.0] * (3 - len(eigs))
+    ang = list(angles) + [0.0] * (3 - len(angles))
+    cz, sz = math.cos(ang[0]), math.sin(ang[0])
+    cy, sy = math.cos(ang[1]), math.sin(ang[1])
+    cx, sx = math.cos(ang[2]), math.sin(ang[2])
+    rz = np.array([[cz, -sz, 0.0], [sz, cz, 0.0], [0.0, 0.0, 1.0]])
+    ry = np.array([[cy, 0.0, sy], [0.0, 1.0, 0.0], [-sy, 0.0, cy]])
+    rx = np.array([[1.0, 0.0, 0.0], [0.0, cx, -sx], [0.0, sx, cx]])
+    r = rx @ ry @ rz
+    t = r @ np.diag(e) @ r.T
+    t = 0.5 * (t + t.T)            # exactly symmetric
+    return t.reshape(-1).tolist()
+
+
 def aniso2d(n: int = 4_000_000, steps: int = 100, precision: int = FP32W_FP64ACC) -> Workload:
-    """rw2d with a diagonal dispersion tensor D_x = 2 D, D_y = D / 2 (the walk
-    and the mass transfer alike): the blob spreads into an ellipse."""
+    """rw2d with a rotated dispersion tensor (principal values 2 and 1/2, axes
+    at 30 degrees; the walk and the mass transfer alike): the blob spreads
+    into a tilted ellipse."""
     w = rw2d(n=n, steps=steps, precision=precision)
-    p = replace(w.params, aniso=[2.0, 0.5, 0.0], seed=0x4D54505407)
-    return Workload("aniso2d", p, w.x0, w.m0, steps, {**w.notes, "aniso": [2.0, 0.5]})
+    p = replace(w.params, disp=rotated_tensor([2.0, 0.5], [math.pi / 6]), seed=0x4D54505407)
+    return Workload("aniso2d", p, w.x0, w.m0, steps, {**w.notes, "disp_eigs": [2.0, 0.5], "angle_deg": 30})
 
 
 WORKLOADS = {"plain2d": plain2d, "rw2d": rw2d, "rw3d": rw3d, "react3d": react3d, "adv2d": adv2d,

@@ -44,7 +44,7 @@ def test_params_struct_matches_header():
     text = open(os.path.join(ROOT, "include", "mtpt.h")).read()
     body = text[text.index("typedef struct {\n    uint32_t abi_version"):text.index("} mtpt_params;")]
     body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
-    fields = re.findall(r"\b(\w+)(?:\[3\])?[,;]", body)
+    fields = re.findall(r"\b(\w+)(?:\[[0-9]\])?[,;]", body)
     names = [f for f, _ in mtpt.mtpt_params._fields_]
     assert [f for f in fields if f in names] == names
 
@@ -74,8 +74,11 @@ def test_validation_rejects_bad_params(lib):
     p = mtpt.make_params(w.params); p.hi[1] = p.lo[1]; cases.append((p, mtpt.MTPT_E_ARG))
     p = mtpt.make_params(w.params); p.start_step = -3; cases.append((p, mtpt.MTPT_E_ARG))
     p = mtpt.make_params(w.params); p.vel[0] = float("inf"); cases.append((p, mtpt.MTPT_E_ARG))
-    p = mtpt.make_params(w.params); p.aniso[0] = 2.0; cases.append((p, mtpt.MTPT_E_ARG))
-    p = mtpt.make_params(w.params); p.aniso[0] = -1.0; p.aniso[1] = 1.0; cases.append((p, mtpt.MTPT_E_ARG))
+    # dispersion tensor: not symmetric, not positive definite, not finite
+    p = mtpt.make_params(w.params); p.disp[0] = 1.0; p.disp[4] = 1.0; p.disp[1] = 0.3; cases.append((p, mtpt.MTPT_E_ARG))
+    p = mtpt.make_params(w.params); p.disp[0] = 1.0; p.disp[4] = -1.0; cases.append((p, mtpt.MTPT_E_ARG))
+    p = mtpt.make_params(w.params); p.disp[0] = 1.0; p.disp[4] = 1.0; p.disp[1] = p.disp[3] = 1.0; cases.append((p, mtpt.MTPT_E_ARG))
+    p = mtpt.make_params(w.params); p.disp[8] = float("nan"); cases.append((p, mtpt.MTPT_E_ARG))
     for p, code in cases:
         rc, h = _call_create(lib, p, x, m)
         assert rc == code and not h.value
@@ -107,3 +110,7 @@ def test_plan_bytes_scale_with_n(lib):
     assert big_b > 8 * small
     p64 = W.with_precision(W.rw2d(n=400_000), W.FP64).params
     assert mtpt.mtpt_sim_bytes(p64) > big_b
+    # a dispersion tensor stretches the cells along its long axis: fewer,
+    # larger cells, so fewer bytes of per-cell tables
+    pt = W.replace(big, disp=W.rotated_tensor([4.0, 1.0], [0.3]))
+    assert mtpt.mtpt_sim_bytes(pt) < big_b

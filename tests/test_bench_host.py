@@ -11,19 +11,31 @@ sys.path.insert(0, ROOT)
 import bench  # noqa: E402
 
 
-def test_transfer_bytes_per_particle():
-    # 2-d FP32W, one species: x 8, s 4, m 8, mask 8 in; m 8 out; jumps 8 in,
-    # walked x 8, cell 4, slot 4 out = 60 B; 2.2e6 cells (rows not trimmed)
-    n = 4_000_000
-    assert bench.algorithmic_bytes("transfer", n, 2, 1, 4, 8, 2_220_000) == 60.0 * n
-    # 3-d with trimmed rows (about 7 particles per cell): three planes of
-    # masks and of recorded windows
-    n3 = 2_000_000
-    b3 = bench.algorithmic_bytes("transfer", n3, 3, 1, 4, 8, 287_000)
-    assert b3 == (12 + 4 + 8 + 24 + 24 + 8 + 12 + 12 + 4 + 4) * n3
-    # short rows (about 1.4 particles per cell): no windows
-    assert bench.algorithmic_bytes("rowsum", 100, 3, 3, 4, 8, 70) == (12 + 4 + 24) * 100
-    assert bench.algorithmic_bytes("scan_down", 10, 2, 1, 4, 8, 1000) == 16.0 * 1000
+def test_step_bytes_follow_the_method():
+    """B = 5 d p + 4 S q + 2 s + 8 per particle-step: 172 B for the 3-d
+    three-species FP32W workload, 240 B in FP64, 88 B for 2-d FP32W."""
+    assert bench.step_bytes(3, 3, 4, 8) == 172.0
+    assert bench.step_bytes(3, 3, 8, 8) == 240.0
+    assert bench.step_bytes(2, 1, 4, 8) == 88.0
+
+
+def test_kernel_shares_add_up_to_the_step():
+    # the three passes' shares of the method's bytes are the whole step
+    for dim, ns, tsz, msz in ((2, 1, 4, 8), (3, 3, 4, 8), (3, 3, 8, 8), (3, 1, 4, 4)):
+        tot = sum(bench.algorithmic_bytes(k, 1000, dim, ns, tsz, msz, 500)
+                  for k in ("place", "rowsum", "transfer"))
+        assert tot == 1000 * bench.step_bytes(dim, ns, tsz, msz)
+    # the transfer of the 3-d three-species FP32W workload: x 12 in, walked x
+    # 12 out, s 4 in, masses 24 in and 24 out
+    assert bench.algorithmic_bytes("transfer", 100, 3, 3, 4, 8, 70) == 76.0 * 100
+    assert bench.algorithmic_bytes("scatter", 100, 3, 3, 4, 8, 70) == 0.0
+    # implementation structures are overhead, listed apart: 3 planes of
+    # neighbour bits, stored jumps, cell and slot; windows only where rows
+    # are trimmed (about 7 particles per cell, not 1.4)
+    o = bench.overhead_bytes("transfer", 100, 3, 3, 4, 8, 70)
+    assert o == {"neighbour_bits": 2400.0, "stored_jumps": 1200.0, "cell_and_slot": 800.0}
+    o7 = bench.overhead_bytes("rowsum", 700, 3, 1, 4, 8, 100)
+    assert o7 == {"neighbour_bits": 700 * 24.0, "row_windows": 700 * 24.0}
 
 
 def test_slots_per_pair():
@@ -35,21 +47,26 @@ def test_slots_per_pair():
     assert bench.algorithmic_slots("place", 10, 100, 2, 1, "fp32w") == 0.0
 
 
-def _res(kernel_ms, pairs, ncells):
+def _res(kernel_ms, pairs, ncells, ms_per_step=1.0):
     return {"phases": {k: (ms, 1) for k, ms in kernel_ms.items()}, "pairs_per_step": pairs,
-            "n_cells": ncells}
+            "n_cells": ncells, "ms_per_step": ms_per_step}
 
 
 def test_roofline_takes_the_longer_ideal_time():
     n = 4_000_000
-    # transfer dominant at 0.09 ms: 240 MB -> 2.67 TB/s; slots 22.6e6 x 20 + 4e6 x 20
-    r = bench.roofline(_res({"transfer": 0.09, "rowsum": 0.08}, 22_600_000, 2_220_000), 2, 1, 4, 8, n)
+    # 2-d FP32W transfer dominant at 0.09 ms: its share 2*8 + 4 + 16 = 36 B
+    # per particle -> 144 MB; slots 22.6e6 x 20 + 4e6 x 20
+    r = bench.roofline(_res({"transfer": 0.09, "rowsum": 0.08}, 22_600_000, 2_220_000, 0.27), 2, 1, 4, 8, n)
     assert r["kernel"] == "transfer"
     assert r["bound"] == "hbm" and r["unit"] == "GB/s"
-    assert r["achieved"] == pytest.approx(240e6 / 0.09e-3 / 1e9, rel=1e-3)
+    assert r["bytes_per_launch"] == 36.0 * n
+    assert r["achieved"] == pytest.approx(36.0 * n / 0.09e-3 / 1e9, rel=1e-3)
     assert r["frac"] == pytest.approx(r["achieved"] / 8000.0, rel=1e-3)
     assert r["ops_per_launch"] == 22_600_000 * 20 + n * 20
     assert r["hbm_frac"] > r["alu_frac"]
+    # the whole step: 88 B per particle over 0.27 ms
+    assert r["step_bytes"] == 88.0 * n
+    assert r["step_frac"] == pytest.approx(88.0 * n / 0.27e-3 / 8e12, rel=1e-3)
     # many pairs per particle: the VALU ideal time is the longer one
     r3 = bench.roofline(_res({"rowsum": 0.3}, 57_200_000 * 4, 287_000), 3, 1, 4, 8, 2_000_000)
     assert r3["bound"] == "alu" and r3["unit"] == "Gop/s"

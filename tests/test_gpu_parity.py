@@ -17,65 +17,13 @@ from paper_2204_03756_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
 
-TOL = {W.FP64: 1e-12, W.FP32W_FP64ACC: 1e-5, W.FP32_KAHAN: 1e-5}
-PREC_NAMES = {W.FP64: "fp64", W.FP32W_FP64ACC: "fp32w", W.FP32_KAHAN: "kahan"}
-
-
-def say(*a):
-    print(*a, flush=True)
-    sys.stdout.flush()
+from gpu_helpers import (PREC_NAMES, TOL, check_parity, gpu_run, load_mt, normwise,  # noqa: E402
+                         oracle_run, say)
 
 
 @pytest.fixture(scope="module")
 def mt():
-    import torch
-    if not torch.cuda.is_available():
-        pytest.skip("no GPU")
-    torch.cuda.set_device(0)
-    from paper_2204_03756_amd import mtpt
-    mtpt.load()
-    return mtpt
-
-
-def normwise(m, ref):
-    out = []
-    for c in range(ref.shape[0]):
-        den = np.max(np.abs(ref[c]))
-        out.append(float(np.max(np.abs(m[c] - ref[c])) / den) if den > 0 else float(np.max(np.abs(m[c]))))
-    return max(out)
-
-
-def gpu_run(mt, w, steps, chunks=None):
-    say(f"  gpu: {w.name} n={w.params.n} prec={PREC_NAMES[w.params.precision]} steps={steps}")
-    alloc = mt.TorchAllocator("cuda:0")
-    with mt.Sim(w.params, w.x0, w.m0, allocator=alloc) as sim:
-        for k in (chunks or [steps]):
-            sim.step(k)
-        return sim.masses(), sim.positions(), sim.stats()
-
-
-def oracle_run(oracle, w, steps, **kw):
-    return oracle.run(w.params, w.x0, w.m0, steps, **kw)
-
-
-def check_parity(mt, oracle, w, steps, bitwise_pos=True):
-    m, x, st = gpu_run(mt, w, steps)
-    ref = oracle_run(oracle, w, steps)
-    err = normwise(m, ref.m)
-    say(f"  {w.name} {PREC_NAMES[w.params.precision]}: normwise {err:.3e}, drift {st['drift']:.3e}, "
-        f"pairs/step {st['pairs_last']}")
-    assert err <= TOL[w.params.precision]
-    if bitwise_pos:
-        assert np.array_equal(x, ref.x)
-    assert st["pairs_last"] == int(ref.pairs[-1])
-    assert st["pairs_total"] == int(ref.pairs.sum())
-    assert st["steps_done"] == steps
-    for c in range(ref.m.shape[0]):
-        # the device's FP64 totals against the oracle's compensated totals,
-        # at the path's bar
-        assert abs(st["mass_total"][c] - ref.totals[-1, c]) <= \
-            TOL[w.params.precision] * max(1.0, abs(ref.totals[-1, c]))
-    return m, x, st, ref
+    return load_mt()
 
 
 # ----------------------------------------------------------------- parity --
@@ -131,6 +79,71 @@ def test_neighbors_bit_exact(mt, oracle, dim, prec):
     assert np.array_equal(row3, orow) and np.array_equal(col3, ocol)
 
 
+def _hot_sets(mt, w, steps):
+    """Positions and the pairs the last step's row-sum and transfer passes used."""
+    alloc = mt.TorchAllocator("cuda:0")
+    with mt.Sim(w.params, w.x0, w.m0, allocator=alloc) as sim:
+        sim.step(steps)
+        x = sim.positions()
+        return x, sim.step_neighbors(0), sim.step_neighbors(1)
+
+
+def _dense3d(n, density, prec):
+    L = (n / density) ** (1.0 / 3.0)
+    p = W.Params(dim=3, n=n, lo=[0.0, 0.0, 0.0], hi=[L, L, L], d_rw=1.0, d_mt=1.0, dt=0.1, beta=0.5,
+                 psi=0.0, seed=0x4D5450540D, precision=prec)
+    rng = np.random.Generator(np.random.Philox(20221203))
+    x = rng.random((n, 3)) * L
+    m = (x[:, 0] < L / 2).astype(np.float64)[None, :]
+    return W.Workload(f"dense3d-rho{density}", p, x, m, 2, {})
+
+
+HOT_CASES = [
+    ("rw2d", W.FP64), ("rw2d", W.FP32W_FP64ACC),
+    ("rw3d", W.FP64), ("rw3d", W.FP32W_FP64ACC), ("rw3d", W.FP32_KAHAN),
+    ("react3d", W.FP64), ("react3d", W.FP32W_FP64ACC),
+    ("dense3d4", W.FP32W_FP64ACC), ("dense3d4", W.FP64), ("dense3d20", W.FP32W_FP64ACC),
+    ("tens3d", W.FP32W_FP64ACC), ("plain2d", W.FP64),
+]
+
+
+@pytest.mark.parametrize("case,prec", HOT_CASES)
+def test_hot_path_neighbor_sets(mt, oracle, case, prec):
+    """Sec. 3, Eq. (1): the neighbour sets that the step's own passes use --
+    the row-sum pass's candidates within the cutoff (trimmed rows in the
+    3-d one-species workload), and the transfer pass's visited pairs (the
+    row-sum pass's neighbour bits decoded over the same candidate rows and
+    windows, or its own candidate loop for waves with more than 64
+    candidates, and the global-memory path for tiles that do not fit the
+    LDS) -- equal the oracle's K-D tree sets at the positions of that step,
+    bit for bit."""
+    if case == "rw2d":
+        w = W.rw2d(n=40_000 + 13, steps=3, precision=prec)
+    elif case == "rw3d":
+        w = W.rw3d(n=30_000 + 19, steps=3, precision=prec, n_src=30)
+    elif case == "react3d":
+        w = W.react3d(n=40_000 + 21, steps=3, precision=prec)
+    elif case == "dense3d4":
+        w = _dense3d(30_000, 4.0, prec)      # rows of ~80: waves past 64 candidates
+    elif case == "dense3d20":
+        w = _dense3d(30_000, 20.0, prec)     # halos beyond the LDS: global path
+    elif case == "tens3d":
+        w0 = W.rw3d(n=20_000 + 7, steps=3, precision=prec, n_src=20)
+        w = W.Workload("tens3d", W.replace(w0.params, disp=W.rotated_tensor([2.5, 0.8, 0.5], [0.4, -0.3, 0.2])),
+                       w0.x0, w0.m0, 3, {})
+    else:
+        w = W.plain2d(n=20_000, steps=3, precision=prec)
+    steps = w.steps if case.startswith("dense") else 3
+    say(f"  hot-path neighbours {case} {PREC_NAMES[prec]} n={w.params.n}")
+    x, rs, tr = _hot_sets(mt, w, steps)
+    ref = oracle_run(oracle, w, steps)
+    assert np.array_equal(x, ref.x)
+    orow, ocol = oracle.neighbors(ref.x, w.params.psi_eff, "kdtree", tens=oracle.tensor_of(w.params))
+    for name, (row, col) in (("row-sum", rs), ("transfer", tr)):
+        assert np.array_equal(row, orow), f"{name} pass: row lengths differ"
+        assert np.array_equal(col, ocol), f"{name} pass: columns differ"
+
+
 def test_neighbors_lattice_ties(mt, oracle):
     """Unit lattice with psi = 1 exactly: the r^2 = psi^2 ties are inside."""
     g = np.stack(np.meshgrid(np.arange(40.0), np.arange(30.0), indexing="xy"), -1).reshape(-1, 2)
@@ -141,8 +154,12 @@ def test_neighbors_lattice_ties(mt, oracle):
             alloc = mt.TorchAllocator("cuda:0")
             with mt.Sim(p, g, np.ones((1, len(g))), allocator=alloc) as sim:
                 row, col = sim.neighbors()
+                sim.step(1)
+                hot = [sim.step_neighbors(0), sim.step_neighbors(1)]
             orow, ocol = oracle.neighbors(g, float(psi), "brute")
             assert np.array_equal(row, orow) and np.array_equal(col, ocol)
+            for hrow, hcol in hot:
+                assert np.array_equal(hrow, orow) and np.array_equal(hcol, ocol)
 
 
 # --------------------------------------------------- determinism / resume --
@@ -262,21 +279,6 @@ def test_dense_tile_global_histogram(mt, oracle, prec):
 
 
 # --------------------------------------------------------------- full size --
-def test_rw2d_full_size_first_steps(mt, oracle):
-    """4e6 particles: the first two steps against the oracle, then 100 steps
-    of invariants (conservation, maximum principle for beta = 1/2)."""
-    for prec in (W.FP32W_FP64ACC, W.FP64):
-        w = W.rw2d(precision=prec)
-        check_parity(mt, oracle, w, 2)
-    w = W.rw2d(precision=W.FP32W_FP64ACC)
-    m, x, st = gpu_run(mt, w, 100)
-    assert st["nonfinite"] == 0
-    assert st["drift"] < 1e-12
-    assert m.min() >= -1e-15 and m.max() <= w.m0.max() * (1 + 1e-12)
-    assert np.all((x >= 0) & (x <= w.params.hi[0]))
-    say(f"  rw2d 100 steps: drift {st['drift']:.3e}, pairs/step {st['pairs_last']}")
-
-
 @pytest.mark.parametrize("dim", [2, 3])
 @pytest.mark.parametrize("prec", [W.FP64, W.FP32W_FP64ACC, W.FP32_KAHAN])
 def test_advection_parity(mt, oracle, dim, prec):
@@ -295,17 +297,30 @@ def test_advection_parity(mt, oracle, dim, prec):
 
 @pytest.mark.parametrize("dim", [2, 3])
 @pytest.mark.parametrize("prec", [W.FP64, W.FP32W_FP64ACC, W.FP32_KAHAN])
-def test_anisotropic_parity(mt, oracle, dim, prec):
-    """Diagonal dispersion tensor (the isotropic step in the scaled frame):
-    positions bit for bit in the caller's frame, masses at the bar; in 3-d
-    with a drift as well."""
+def test_tensor_parity(mt, oracle, dim, prec):
+    """Dispersion tensor (Cholesky jumps, Mahalanobis kernel, ellipsoidal
+    cutoff, all in the caller's frame): positions bit for bit, masses at the
+    bar, neighbour sets bit-exact; a rotated tensor in 2-d, and in 3-d a
+    rotated one with a drift and a diagonal one."""
     if dim == 2:
         w = W.aniso2d(n=30_000 + 29, steps=6, precision=prec)
+        check_parity(mt, oracle, w, 6, nb=True)
     else:
         w0 = W.rw3d(n=20_000 + 7, steps=6, precision=prec, n_src=20)
-        p = W.replace(w0.params, aniso=[1.5, 0.8, 0.5], vel=[1.0, 0.0, -2.0])
-        w = W.Workload("aniso3d", p, w0.x0, w0.m0, 6, {})
-    check_parity(mt, oracle, w, 6)
+        p = W.replace(w0.params, disp=W.rotated_tensor([2.5, 0.8, 0.5], [0.4, -0.3, 0.2]), vel=[1.0, 0.0, -2.0])
+        check_parity(mt, oracle, W.Workload("tens3d", p, w0.x0, w0.m0, 6, {}), 6, nb=True)
+        p = W.replace(w0.params, disp=W.diag_tensor([1.5, 0.8, 0.5]))
+        check_parity(mt, oracle, W.Workload("diag3d", p, w0.x0, w0.m0, 6, {}), 6, nb=True)
+
+
+@pytest.mark.parametrize("prec", [W.FP64, W.FP32W_FP64ACC])
+def test_tensor_reaction_parity(mt, oracle, prec):
+    """Three species with A+B->C under a dispersion tensor of determinant
+    != 1: the reaction's concentrations use the box volume (the oracle
+    computes them from the caller's box by definition)."""
+    w0 = W.react3d(n=40_000 + 11, steps=4, precision=prec)
+    p = W.replace(w0.params, disp=W.rotated_tensor([3.0, 1.5, 0.6], [0.5, 0.1, -0.2]))
+    check_parity(mt, oracle, W.Workload("tens-react3d", p, w0.x0, w0.m0, 4, {}), 4)
 
 
 @pytest.mark.parametrize("prec", [W.FP64, W.FP32W_FP64ACC])
@@ -323,43 +338,3 @@ def test_sparse_grid_many_scan_tiles(mt, oracle, prec):
     w = W.Workload("sparse2d", p, x, m, 3, {})
     m_, x_, st, ref = check_parity(mt, oracle, w, 3)
     assert st["n_cells"] + 1 > 2048 * 4096
-
-
-def test_rw3d_full_size_first_step(mt, oracle):
-    w = W.rw3d(precision=W.FP32W_FP64ACC)
-    check_parity(mt, oracle, w, 1)
-    w = W.rw3d(precision=W.FP32_KAHAN)
-    m, x, st = gpu_run(mt, w, 100)
-    assert st["nonfinite"] == 0 and st["drift"] < 1e-4
-    assert m.min() >= -1e-9
-    say(f"  rw3d kahan 100 steps: drift {st['drift']:.3e}")
-
-
-def test_react3d_full_size_invariants(mt, oracle):
-    """3.2e7 particles, three species: positions of sampled pids against the
-    oracle's walk after one step, and the reaction/transfer invariants after
-    20 steps."""
-    w = W.react3d(precision=W.FP32W_FP64ACC)
-    m, x, st = gpu_run(mt, w, 1)
-    rng = np.random.default_rng(0)
-    sample = rng.choice(w.params.n, 2000, replace=False)
-    x32 = w.x0[sample].astype(np.float32).astype(np.float64)
-    # the oracle's normals of the sampled pids, walked in float as the FP32
-    # state requires
-    for k, pid in enumerate(sample[:200]):
-        z0, z1 = oracle.normal_pair(w.params.seed, 0, int(pid), 0)
-        z2, _ = oracle.normal_pair(w.params.seed, 0, int(pid), 1)
-        exp = []
-        for d, z in enumerate((z0, z1, z2)):
-            v = np.float32(x32[k, d]) + np.float32(z * math.sqrt(2.0 * w.params.d_rw * w.params.dt))
-            lo, hi = np.float32(0.0), np.float32(w.params.hi[d])
-            while v < lo or v > hi:
-                v = np.float32(2.0) * lo - v if v < lo else np.float32(2.0) * hi - v
-            exp.append(float(v))
-        assert np.array_equal(x[pid], exp)
-    m, x, st = gpu_run(mt, w, 20)
-    assert st["nonfinite"] == 0
-    ta, tb = m[0].sum() + m[2].sum(), m[1].sum() + m[2].sum()
-    assert abs(ta / w.m0[0].sum() - 1) < 1e-9 and abs(tb / w.m0[1].sum() - 1) < 1e-9
-    assert m[2].sum() > 0 and m.min() > -1e-12
-    say(f"  react3d 20 steps: C total {m[2].sum():.6e}")

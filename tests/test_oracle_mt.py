@@ -325,63 +325,186 @@ def test_drift_translates_the_erfc_profile(oracle):
     assert abs(res.totals[-1, 0] - w.m0.sum()) <= 1e-12 * w.m0.sum()
 
 
-# ----------------------------------------------- anisotropic dispersion ----
-def test_anisotropic_pair_closed_form(oracle):
-    """A diagonal dispersion tensor D_k = a_k D: a pair at distance r along
-    axis k exchanges with K = exp(-beta r^2 / (4 a_k D_MT dt)), and the cutoff
-    is the ellipsoid sum_k dx_k^2 / a_k <= psi^2."""
-    d_mt, dt, beta, r = 0.7, 0.1, 0.5, 0.9
-    a = [4.0, 0.25]
+# ------------------------------------------------- dispersion tensor ----
+def _spd(rng, dim, cond=8.0):
+    """A random symmetric positive-definite [3][3] tensor (2-d: 2x2 block used)."""
+    q, _ = np.linalg.qr(rng.standard_normal((dim, dim)))
+    ev = np.exp(rng.uniform(0.0, math.log(cond), dim))
+    t = q @ np.diag(ev) @ q.T
+    t = 0.5 * (t + t.T)
+    t3 = np.eye(3)
+    t3[:dim, :dim] = t
+    return t3
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_tensor_distance_is_mahalanobis(oracle, dim):
+    """The cutoff metric under a shape tensor T is dx^T T^-1 dx (numpy's
+    inverse as the reference), and T = I gives the Euclidean r^2 bit for bit."""
+    rng = np.random.default_rng(31 + dim)
+    for _ in range(20):
+        t = _spd(rng, dim)
+        ti = np.linalg.inv(t[:dim, :dim])
+        for _ in range(20):
+            xi = rng.uniform(-5, 5, dim)
+            xj = xi + rng.normal(0, 1.5, dim)
+            dx = xj - xi
+            ref = dx @ ti @ dx
+            assert oracle.pair_dist2(xi, xj, t) == pytest.approx(ref, rel=1e-12)
+    for _ in range(50):
+        xi = rng.uniform(-5, 5, dim)
+        xj = xi + rng.normal(0, 1.5, dim)
+        assert oracle.pair_dist2(xi, xj, np.eye(3)) == oracle.pair_dist2(xi, xj, None)
+    bad = np.eye(3); bad[0, 1] = 0.5   # not symmetric
+    with pytest.raises(ValueError):
+        oracle.pair_dist2(np.zeros(dim), np.ones(dim), bad)
+    neg = np.eye(3); neg[1, 1] = -1.0
+    with pytest.raises(ValueError):
+        oracle.pair_dist2(np.zeros(dim), np.ones(dim), neg)
+
+
+@pytest.mark.parametrize("dim,n", [(2, 3000), (3, 4000)])
+def test_tensor_neighbors_equal_brute_force(oracle, dim, n):
+    """Ellipsoidal cutoff: the K-D tree (pruned by the ellipsoid's reach along
+    each axis) and the brute-force search give the set of pairs with
+    dx^T T^-1 dx <= psi^2, computed here with numpy's inverse (pairs within
+    1e-9 of the cutoff are left out of the comparison)."""
+    rng = np.random.default_rng(7 * dim)
+    L = n ** (1.0 / dim)
+    x = rng.uniform(0, L, (n, dim))
+    t = _spd(rng, dim, cond=10.0)
+    psi = 1.3
+    rb, cb = oracle.neighbors(x, psi, "brute", tens=t)
+    rk, ck = oracle.neighbors(x, psi, "kdtree", tens=t)
+    assert np.array_equal(rb, rk) and np.array_equal(cb, ck)
+    ti = np.linalg.inv(t[:dim, :dim])
+    rows = np.repeat(np.arange(n), np.diff(rk))
+    got = set(zip(rows.tolist(), ck.tolist()))
+    # reference: all pairs (chunked), with numpy's quadratic form
+    for i0 in range(0, n, 500):
+        dx = x[None, :, :] - x[i0:i0 + 500, None, :]
+        q = np.einsum("abk,kl,abl->ab", dx, ti, dx)
+        ii, jj = np.nonzero(q <= psi * psi * (1 - 1e-9))
+        for i, j in zip((ii + i0).tolist(), jj.tolist()):
+            assert (i, j) in got
+        ii, jj = np.nonzero(q <= psi * psi * (1 + 1e-9))
+        assert sum(1 for i, j in zip((ii + i0).tolist(), jj.tolist()) if (i, j) in got) == \
+            sum(1 for r in range(i0, min(n, i0 + 500)) for _ in range(rk[r + 1] - rk[r]))
+
+
+def test_tensor_pair_closed_form(oracle):
+    """A pair at distance r along principal axis e_k (eigenvalue l_k) of a
+    rotated tensor exchanges with K = exp(-beta r^2 / (4 l_k D_MT dt)); the
+    cutoff r^2 / l_k <= psi^2 keeps it or drops it.  The positions do not
+    move without a walk."""
+    d_mt, dt, beta = 0.7, 0.1, 0.5
+    eig = [4.0, 0.25]
+    ang = 0.4
+    t = W.rotated_tensor(eig, [ang])
+    e = [np.array([math.cos(ang), math.sin(ang)]), np.array([-math.sin(ang), math.cos(ang)])]
     m = np.array([[0.3, 1.7]])
-    for axis in (0, 1):
-        x = np.array([[10.0, 10.0], [10.0, 10.0]])
-        x[1, axis] += r
-        p = W.Params(dim=2, n=2, lo=[0.0, 0.0, 0.0], hi=[20.0, 20.0, 0.0], d_rw=0.0, d_mt=d_mt,
-                     dt=dt, beta=beta, psi=2.0, aniso=[a[0], a[1], 0.0])
-        res = oracle.run(p, x, m, 1, method="brute")
-        K = math.exp(-beta * r * r / (4 * a[axis] * d_mt * dt))
-        expect = 0.3 + beta * K / (1 + K) * (1.7 - 0.3)
-        if r * r / a[axis] <= 2.0 ** 2:
-            assert res.pairs[0] == 2
-            assert res.m[0, 0] == pytest.approx(expect, rel=1e-14)
-            assert res.m[0, 1] == pytest.approx(2.0 - expect, rel=1e-14)
-        else:
-            assert res.pairs[0] == 0 and np.array_equal(res.m, m)
-        assert np.array_equal(res.x, x)
-    # along y the ellipse is 4x narrower: a pair at 0.9 in y (0.9^2/0.25 = 3.24)
-    # interacts with psi = 2, one at 1.1 (4.84 > 4) does not
-    x = np.array([[10.0, 10.0], [10.0, 11.1]])
-    p = W.Params(dim=2, n=2, lo=[0.0, 0.0, 0.0], hi=[20.0, 20.0, 0.0], d_rw=0.0, d_mt=d_mt,
-                 dt=dt, beta=beta, psi=2.0, aniso=[a[0], a[1], 0.0])
-    assert oracle.run(p, x, m, 1, method="brute").pairs[0] == 0
+    for k in (0, 1):
+        for r in (0.45, 0.9, 1.1, 3.5):
+            x = np.array([[10.0, 10.0], [10.0, 10.0]]) + np.array([[0.0, 0.0], r * e[k]])
+            p = W.Params(dim=2, n=2, lo=[0.0, 0.0, 0.0], hi=[20.0, 20.0, 0.0], d_rw=0.0, d_mt=d_mt,
+                         dt=dt, beta=beta, psi=2.0, disp=t)
+            res = oracle.run(p, x, m, 1, method="brute")
+            if r * r / eig[k] <= 4.0 * (1 - 1e-9):
+                K = math.exp(-beta * r * r / (4 * eig[k] * d_mt * dt))
+                expect = 0.3 + beta * K / (1 + K) * (1.7 - 0.3)
+                assert res.pairs[0] == 2
+                assert res.m[0, 0] == pytest.approx(expect, rel=1e-12)
+                assert res.m[0, 1] == pytest.approx(2.0 - expect, rel=1e-12)
+            elif r * r / eig[k] > 4.0 * (1 + 1e-9):
+                assert res.pairs[0] == 0 and np.array_equal(res.m, m)
+            assert np.array_equal(res.x, x)
 
 
-def test_anisotropic_spreading_rates(oracle):
-    """Heaviside fronts across x and across y spread with D_x / D_y = a_x / a_y
-    (the erfc fit of Sec. 2.1 along each axis): at density 10 each fitted D
-    is a_k times the mean-field effective D of the isotropic frame, within the
-    bounds the isotropic test uses (a_x a_y = 1 keeps the frame's density)."""
+@pytest.mark.parametrize("dim", [2, 3])
+def test_tensor_walk_covariance(oracle, dim):
+    """The jumps under a shape tensor T have covariance 2 d_rw dt T (their
+    sample covariance within 5 standard errors of every entry), so the walk
+    realises D_RW = d_rw T; the walls stay mirrors of the box."""
+    rng = np.random.default_rng(5 + dim)
+    t = _spd(rng, dim, cond=6.0)
+    n = 200_000
+    L = 1000.0
+    x = np.full((n, dim), L / 2)
+    d_rw, dt = 0.8, 0.1
+    lo = [0.0] * dim
+    hi = [L] * dim
+    y = oracle.rw_step(x, lo, hi, d_rw, dt, 77, 3, tens=t)
+    d = y - x
+    c = np.cov(d.T, bias=True)
+    ref = 2 * d_rw * dt * t[:dim, :dim]
+    # standard error of a sample covariance entry: sqrt((S_kk S_ll + S_kl^2) / n)
+    se = np.sqrt((np.outer(np.diag(ref), np.diag(ref)) + ref * ref) / n)
+    assert np.all(np.abs(c - ref) < 5 * se)
+    assert np.all(np.abs(d.mean(axis=0)) < 5 * np.sqrt(np.diag(ref) / n))
+    # reflection keeps the box: start next to the lower walls
+    x0 = np.full((2000, dim), 0.05)
+    y0 = oracle.rw_step(x0, lo, hi, 50.0, 1.0, 78, 0, tens=t)
+    assert np.all(y0 >= 0.0) and np.all(y0 <= L)
+    # the identity tensor is the isotropic walk, bit for bit
+    yi = oracle.rw_step(x[:5000], lo, hi, d_rw, dt, 77, 3, tens=np.eye(3))
+    yn = oracle.rw_step(x[:5000], lo, hi, d_rw, dt, 77, 3)
+    assert np.array_equal(yi, yn)
+
+
+def test_tensor_spreading_rates(oracle):
+    """A Heaviside front whose normal is principal axis e_k of a rotated
+    tensor spreads as 1/2 erfc(s / sqrt(4 D t)) along e_k with D = l_k times
+    the isotropic mean-field effective D (det T = 1 keeps the density of the
+    whitened frame), for both axes (the erfc fit of Sec. 2.1 along each)."""
     n = 40_000
     L = math.sqrt(n / 10.0)
     w = W.plain2d(n=n)
     x0 = w.x0 * (L / w.params.hi[0])
-    ax, ay = 2.0, 0.5
-    p = W.Params(**{**w.params.as_dict(), "hi": [L, L, 0.0], "aniso": [ax, ay, 0.0]})
-    t = 50 * p.dt
+    eig = [2.0, 0.5]
+    ang = math.pi / 6
+    t = W.rotated_tensor(eig, [ang])
+    e = [np.array([math.cos(ang), math.sin(ang)]), np.array([-math.sin(ang), math.cos(ang)])]
+    p = W.Params(**{**w.params.as_dict(), "hi": [L, L, 0.0], "disp": t})
+    tt = 50 * p.dt
     d_mf = _d_eff_mean_field(10.0, p.d_mt, p.dt, p.beta, p.psi_eff, 2)
+    c = np.array([L / 2, L / 2])
+    central = np.linalg.norm(x0 - c, axis=1) < L / 3
     fits = []
-    for axis, a in ((0, ax), (1, ay)):
-        m0 = (x0[:, axis] < L / 2).astype(np.float64)[None, :]
+    for k in (0, 1):
+        s = (x0 - c) @ e[k]
+        m0 = (s < 0).astype(np.float64)[None, :]
         res = oracle.run(p, x0, m0, 50)
-        xs = x0[:, [axis, 1 - axis]]
+        mask = central & (np.abs(s) < 15.0)
         Ds = np.linspace(0.05, 3.0, 1181)
-        mask = np.abs(xs[:, 0] - L / 2) < 15.0
-        err = [np.mean((res.m[0][mask] - 0.5 * special.erfc((xs[mask, 0] - L / 2) /
-                                                             math.sqrt(4 * D * t))) ** 2) for D in Ds]
+        err = [np.mean((res.m[0][mask] - 0.5 * special.erfc(s[mask] / math.sqrt(4 * D * tt))) ** 2)
+               for D in Ds]
         d_fit = Ds[int(np.argmin(err))]
-        assert 0.90 * a * d_mf < d_fit <= 1.02 * a * d_mf
+        assert 0.90 * eig[k] * d_mf < d_fit <= 1.02 * eig[k] * d_mf
         fits.append(d_fit)
-    assert fits[0] / fits[1] == pytest.approx(ax / ay, rel=0.1)
+    assert fits[0] / fits[1] == pytest.approx(eig[0] / eig[1], rel=0.1)
+
+
+def test_tensor_reaction_uses_the_box_volume(oracle):
+    """With a dispersion tensor of determinant 8 and A+B->C, a well-mixed field
+    (equal masses everywhere, so the transfer moves nothing) reacts on the
+    concentrations c = N M / V of the simulation's own box volume V (Sec. 3's
+    mass-to-concentration map): one step gives a0 / (1 + k a0 dt)."""
+    n = 3000
+    Lx, Ly, Lz = 30.0, 10.0, 10.0
+    rng = np.random.default_rng(3)
+    x = rng.uniform(0, 1, (n, 3)) * [Lx, Ly, Lz]
+    t = W.rotated_tensor([4.0, 2.0, 1.0], [0.3, 0.2, 0.1])
+    m0 = np.zeros((3, n))
+    m0[0] = m0[1] = 0.7
+    k, dt = 1.3, 0.05
+    p = W.Params(dim=3, n=n, lo=[0.0, 0.0, 0.0], hi=[Lx, Ly, Lz], d_rw=0.0, d_mt=0.5, dt=dt,
+                 beta=0.5, psi=0.0, k_react=k, n_species=3, disp=t)
+    res = oracle.run(p, x, m0, 1)
+    V = Lx * Ly * Lz
+    a0 = 0.7 * n / V
+    a1 = a0 / (1 + k * a0 * dt)
+    assert np.allclose(res.m[0] * n / V, a1, rtol=1e-12, atol=0)
+    assert np.allclose(res.m[2] * n / V, a0 - a1, rtol=1e-12, atol=0)
 
 
 # ------------------------------------------------------------ reaction ----
