@@ -124,36 +124,54 @@ typedef struct {
     int32_t n_cells;        /* cells of the binning grid (side >= psi) */
 } mtpt_stats_t;
 
-/* Create a simulation (Sec. 3 state: positions, masses, parameters).
- * pos: host FP64 [n][dim]; every coordinate within [lo, hi].
- * mass: host FP64 [n_species][n].
+/* Create a simulation: the particle state of Sec. 3 (positions X_i and
+ * masses M_i of N particles in the box, Sec. 2.1) and its parameters
+ * (D_RW, D_MT, dt, beta, the search radius psi of Eq. (1)).
+ * pos: host FP64 [n][dim], row-major, every coordinate within [lo, hi].
+ * mass: host FP64 [n_species][n], species-major, finite.
  * hip_stream: a hipStream_t, or NULL for a library-owned stream.
  * alloc: device allocator, or NULL for hipMalloc/hipFree.
- * Enqueues the first cell binning and the initial mass totals.
+ * The library copies pos and mass (host staging, then device copies), bins
+ * the particles into cells, computes the initial mass totals, and waits for
+ * that work before returning; the sim owns all its device memory.
  * Errors: MTPT_E_ABI, MTPT_E_ARG (dim, n, species, precision, box, dt, d_mt,
- * d_rw, beta, k_react out of range, or a position outside the box),
- * MTPT_E_NOMEM, MTPT_E_DEVICE.  *out is NULL on error. */
+ * d_rw, beta, k_react, vel or disp out of range, a position outside the box,
+ * a non-finite mass), MTPT_E_NOMEM, MTPT_E_DEVICE.  *out is NULL on error. */
 int mtpt_create(const mtpt_params* params, const double* pos, const double* mass,
                 void* hip_stream, const mtpt_allocator* alloc, mtpt_sim** out);
 
-/* Enqueue n_steps full steps (walk, binning, row sums, exchange, reaction,
- * totals) on the sim's stream; returns without waiting.  n_steps >= 0. */
+/* Enqueue n_steps full steps of Sec. 3 on the sim's stream: the random walk
+ * with reflecting walls, the neighbour search within psi (Eq. (1)), the
+ * kernel weights and row sums (Eq. (2)-(3)), the symmetric normalisation
+ * and the explicit mass exchange (Eq. (4)-(5)), the optional A+B->C
+ * reaction, and the FP64 mass totals.  Returns without waiting; a later
+ * synchronising call reports device errors.  n_steps >= 0, else
+ * MTPT_E_ARG; MTPT_E_DEVICE if a launch fails. */
 int mtpt_step(mtpt_sim* sim, int64_t n_steps);
 
-/* Masses after the last step, FP64 [n_species][n], original order.
- * Synchronises.  Returns MTPT_E_NONFINITE if a mass total was non-finite. */
+/* Masses M_i after the last step (Eq. (5); with three species A, B, C after
+ * the reaction), into the caller's host buffer out: FP64 [n_species][n] in
+ * the original particle order.  Synchronises.  MTPT_E_NONFINITE (out still
+ * written) if a mass total became NaN or infinite; MTPT_E_ARG for NULL. */
 int mtpt_masses(mtpt_sim* sim, double* out);
 
-/* Positions after the last step, FP64 [n][dim], original order.  Synchronises. */
+/* Positions X_i after the last step's random walk (Sec. 3), into the
+ * caller's host buffer out: FP64 [n][dim] in the original particle order
+ * (FP32 state converted exactly in the FP32 modes).  Synchronises. */
 int mtpt_positions(mtpt_sim* sim, double* out);
 
-/* Counters and totals (see mtpt_stats_t).  Synchronises. */
+/* Counters and totals (see mtpt_stats_t): ordered pairs within psi per step
+ * (Eq. (1)) and the FP64 mass totals, whose conservation follows from the
+ * symmetry of W (Sec. 3).  Synchronises. */
 int mtpt_stats(mtpt_sim* sim, mtpt_stats_t* out);
 
-/* Neighbour sets at the current positions (Sec. 3, r^2 <= psi^2, inclusive,
- * self included), as CSR in original order with each row ascending:
- * row_ptr[n+1] (always written), col[nnz] written only when nnz <= cap.
- * *nnz_out receives nnz.  Synchronises.  A debug/test export, not a step. */
+/* Neighbour sets at the current positions (Sec. 3, Eq. (1): r^2 <= psi^2,
+ * inclusive, self included; the ellipsoid q <= psi^2 with a dispersion
+ * tensor), found by a plain scan of the 3^d cells around each particle, as
+ * CSR in original order with each row ascending: row_ptr[n+1] (host, always
+ * written), col[nnz] (host) written only when nnz <= cap, *nnz_out = nnz.
+ * Scratch device memory comes from the sim's allocator (MTPT_E_NOMEM).
+ * Synchronises.  A debug/test export, not a step. */
 int mtpt_neighbors(mtpt_sim* sim, int64_t* row_ptr, int64_t* col, int64_t cap, int64_t* nnz_out);
 
 /* Neighbour sets exactly as a hot pass of the last step used them, in the
@@ -169,8 +187,9 @@ int mtpt_neighbors(mtpt_sim* sim, int64_t* row_ptr, int64_t* col, int64_t cap, i
 int mtpt_step_neighbors(mtpt_sim* sim, int32_t which, int64_t* row_ptr, int64_t* col, int64_t cap,
                         int64_t* nnz_out);
 
-/* Free the sim's device memory (and stream, if library-owned).  NULL is a
- * no-op.  Synchronises on the sim's stream first. */
+/* Free the sim's device memory (and stream, if library-owned); the handle
+ * is invalid afterwards.  NULL is a no-op.  Synchronises on the sim's
+ * stream first. */
 int mtpt_destroy(mtpt_sim* sim);
 
 /* Message of the last error on this thread ("" if none). */
@@ -179,28 +198,35 @@ const char* mtpt_last_error(void);
 /* MTPT_ABI_VERSION the library was built with. */
 int mtpt_abi_version(void);
 
-/* Per-phase device time: when enabled, HIP events bracket every kernel the
- * sim launches and their durations are accumulated per phase.  names[k] and
- * ms[k], k < *count, receive phase name, total milliseconds and launch count.
+/* Per-phase device time (measurement, no passage of the paper): when
+ * enabled, HIP events bracket every kernel the sim launches and their
+ * durations are accumulated per phase.  names[k], ms[k] and launches[k],
+ * k < min(*count, cap), receive the phase name (static string), total
+ * milliseconds and launch count; any of the three may be NULL.
  * mtpt_phase_times synchronises and resets the accumulators. */
 int mtpt_set_profiling(mtpt_sim* sim, int32_t on);
 int mtpt_phase_times(mtpt_sim* sim, const char** names, double* ms, int64_t* launches,
                      int32_t cap, int32_t* count);
 
 /* ---------------------------------------------------------------------
- * Serving: a pool of independent simulations of any size and dimension,
- * admitted while device memory and slots allow, stepped together: one tick
- * advances every active sim by one step with one batched launch per phase.
+ * Serving (no passage of the paper: independent simulations of Sec. 3 run
+ * side by side): a pool of simulations of any size and dimension, admitted
+ * while device memory and slots allow, stepped together: one tick advances
+ * every active sim by one step with one batched launch per phase.  Each
+ * sim's result is bit-identical to the same sim run alone.
  * --------------------------------------------------------------------- */
 
 /* hbm_budget: bytes of device memory the pool may hold (0: 90 % of free
- * memory at create).  max_slots: most sims active at once (>= 1). */
+ * memory at create).  max_slots: most sims active at once (>= 1, else
+ * MTPT_E_ARG).  hip_stream and alloc as for mtpt_create. */
 int mtpt_pool_create(size_t hbm_budget, int32_t max_slots, void* hip_stream,
                      const mtpt_allocator* alloc, mtpt_pool** out);
 
-/* Admit a sim that will run n_steps (>= 1) steps.  *ticket identifies it.
- * Returns MTPT_E_NOMEM when the slots or the budget cannot hold it now (retry
- * after a result has been collected); other errors as mtpt_create. */
+/* Admit a sim (params, pos and mass as for mtpt_create) that will run
+ * n_steps (>= 1) steps; *ticket identifies it.  Its bytes are those of
+ * mtpt_sim_bytes plus n_species * n * 8 of result staging.  Returns
+ * MTPT_E_NOMEM when the slots or the budget cannot hold it now (retry after
+ * a result has been collected); other errors as mtpt_create. */
 int mtpt_pool_admit(mtpt_pool* pool, const mtpt_params* params, const double* pos,
                     const double* mass, int64_t n_steps, int64_t* ticket);
 
@@ -209,23 +235,30 @@ int mtpt_pool_admit(mtpt_pool* pool, const mtpt_params* params, const double* po
  * Returns without waiting. */
 int mtpt_pool_tick(mtpt_pool* pool, int32_t* n_completed);
 
-/* 1 in *done if the ticket's sim has taken all its steps (synchronises). */
+/* 1 in *done if the ticket's sim has taken all its steps (synchronises
+ * then), else 0.  MTPT_E_ARG for an unknown ticket. */
 int mtpt_pool_done(mtpt_pool* pool, int64_t ticket, int32_t* done);
 
-/* Counters and totals of an admitted sim (see mtpt_stats_t).  Synchronises. */
+/* Counters and totals of an admitted sim (see mtpt_stats_t).  Synchronises.
+ * MTPT_E_ARG for an unknown ticket. */
 int mtpt_pool_stats(mtpt_pool* pool, int64_t ticket, mtpt_stats_t* out);
 
-/* Copy a finished sim's masses (FP64 [n_species][n], original order) and
- * free its slot and memory.  Synchronises.  MTPT_E_STATE if not finished. */
+/* Copy a finished sim's masses (as mtpt_masses: host FP64 [n_species][n],
+ * original order) into mass_out and free its slot and memory; the ticket is
+ * invalid afterwards.  Synchronises.  MTPT_E_STATE if not finished,
+ * MTPT_E_ARG for an unknown ticket. */
 int mtpt_pool_result(mtpt_pool* pool, int64_t ticket, double* mass_out);
 
-/* Active sims, bytes held, budget. */
+/* Active sims, bytes held, budget (any pointer may be NULL). */
 int mtpt_pool_usage(mtpt_pool* pool, int32_t* active, size_t* bytes_held, size_t* budget);
 
-/* Bytes of device memory a sim with these params needs (for admission). */
+/* Bytes of device memory a sim with these params allocates at create (its
+ * particle arrays, cell tables and scratch; for admission).  Errors as the
+ * parameter checks of mtpt_create. */
 int mtpt_sim_bytes(const mtpt_params* params, size_t* bytes);
 
-/* Free every sim of the pool and the pool.  NULL is a no-op. */
+/* Free every sim of the pool and the pool (synchronises first).  NULL is a
+ * no-op. */
 int mtpt_pool_destroy(mtpt_pool* pool);
 
 #ifdef __cplusplus

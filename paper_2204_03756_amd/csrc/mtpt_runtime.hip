@@ -699,8 +699,10 @@ void release(mtpt_sim* s)
     delete s;
 }
 
-// Upload inputs and bin them (the state at step 0).  The host staging is in
-// pinned memory so the copies run asynchronously; create waits at the end.
+// Upload inputs and bin them (the state at step 0).  Positions (and Kahan
+// masses) are converted on the host into pageable staging and copied with
+// blocking copies; the binning and the initial totals are enqueued on the
+// sim's stream, and create waits for them (the initial totals are read back).
 int create_into(mtpt_sim* s, const double* pos, const double* mass)
 {
     const Plan& q = s->q;
