@@ -174,6 +174,19 @@ int mtpt_stats(mtpt_sim* sim, mtpt_stats_t* out);
  * Synchronises.  A debug/test export, not a step. */
 int mtpt_neighbors(mtpt_sim* sim, int64_t* row_ptr, int64_t* col, int64_t cap, int64_t* nnz_out);
 
+/* mtpt_neighbors for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same result, with every byte of device scratch (row counts, scan
+ * tiles, the device row offsets and columns) carved from one static array
+ * of 64 MiB that each GPU the library runs on holds until the process ends.
+ * It calls no hipMalloc, hipFree or allocator.  Sizes beyond the array are
+ * rejected with MTPT_E_ARG: 16 n + 8 nnz bytes (plus scan padding) must fit,
+ * checked before any device work for the rows and again, after row_ptr is
+ * written, for the columns.  Every call on a GPU shares that GPU's array:
+ * calls that overlap on one GPU (other threads, other streams) race; the
+ * call synchronises the sim's stream before it returns. */
+int mtpt_neighbors_static(mtpt_sim* sim, int64_t* row_ptr, int64_t* col, int64_t cap, int64_t* nnz_out);
+
 /* Neighbour sets exactly as a hot pass of the last step used them, in the
  * CSR format of mtpt_neighbors (pid order, rows ascending, self included):
  * which = 0: the row-sum pass (every candidate it found within the cutoff,

@@ -17,6 +17,7 @@
 #include <cstring>
 #include <deque>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -371,6 +372,7 @@ struct PhaseEv {
 struct mtpt_sim {
     mtpt_params p{};
     Tensor tens;              // dispersion tensor (isotropic: tens.on == false)
+    int device = 0;           // the HIP device current at create
     Plan q;
     Alloc alloc;
     hipStream_t stream = nullptr;
@@ -802,6 +804,10 @@ int new_sim(const mtpt_params* params, const double* pos, const double* mass, vo
         const char* why = "";
         (void)tensor_of(s->p, &s->tens, &why);   // validated above
     }
+    if (hipGetDevice(&s->device) != hipSuccess) {
+        delete s;
+        return fail(MTPT_E_DEVICE, "hipGetDevice failed");
+    }
     s->q = make_plan(s->p);
     s->moving = s->p.d_rw > 0.0;
     for (int k = 0; k < params->dim; ++k)
@@ -983,21 +989,59 @@ namespace {
 // CSR export in pid order: count(rowcnt) fills rowcnt[pid] with each row's
 // length, fill(row_ptr, col) writes the rows (sorted ascending) from device
 // row offsets.  Scratch comes from the sim's allocator.
+// Device scratch of a CSR export: from the sim's allocator, or carved in
+// order from one fixed buffer (base != nullptr; nothing is allocated or
+// freed then, and a request beyond its size fails).
+struct CsrScratch {
+    mtpt_sim* s;
+    char* base = nullptr;
+    size_t size = 0;
+    size_t used = 0;
+    void* get(size_t bytes)
+    {
+        if (!base)
+            return s->alloc.get(bytes);
+        const size_t need = align_up(used, 256) + bytes;
+        if (need > size)
+            return nullptr;
+        void* p = base + align_up(used, 256);
+        used = need;
+        return p;
+    }
+    void put(void* p)
+    {
+        if (!base)
+            s->alloc.put(p);
+    }
+};
+
+// Bytes of fixed scratch a CSR export of n rows and nnz entries needs.
+size_t csr_scratch_bytes(int64_t n, int64_t nnz)
+{
+    const size_t tiles = static_cast<size_t>((n + 1 + kScanTile - 1) / kScanTile);
+    return align_up(static_cast<size_t>(n) * 4, 256) + align_up(tiles * kScanTile * 4, 256) +
+           align_up(tiles * 4, 256) + align_up(static_cast<size_t>(n + 1) * 8, 256) +
+           static_cast<size_t>(nnz) * 8;
+}
+
 template <typename Count, typename Fill>
 int csr_export(mtpt_sim* s, int64_t* row_ptr, int64_t* col, int64_t cap, int64_t* nnz_out, Count count,
-               Fill fill)
+               Fill fill, char* fixed = nullptr, size_t fixed_bytes = 0)
 {
     const int64_t n = s->q.n;
     const int64_t tiles = (n + 1 + kScanTile - 1) / kScanTile;
-    uint32_t* rowcnt = static_cast<uint32_t*>(s->alloc.get(static_cast<size_t>(n) * 4));
-    uint32_t* tmp = static_cast<uint32_t*>(s->alloc.get(static_cast<size_t>(tiles) * kScanTile * 4));
-    uint32_t* bs = static_cast<uint32_t*>(s->alloc.get(static_cast<size_t>(tiles) * 4));
-    int64_t* drp = static_cast<int64_t*>(s->alloc.get(static_cast<size_t>(n + 1) * 8));
+    CsrScratch sc{s, fixed, fixed_bytes};
+    uint32_t* rowcnt = static_cast<uint32_t*>(sc.get(static_cast<size_t>(n) * 4));
+    uint32_t* tmp = static_cast<uint32_t*>(sc.get(static_cast<size_t>(tiles) * kScanTile * 4));
+    uint32_t* bs = static_cast<uint32_t*>(sc.get(static_cast<size_t>(tiles) * 4));
+    int64_t* drp = static_cast<int64_t*>(sc.get(static_cast<size_t>(n + 1) * 8));
     int64_t* dcol = nullptr;
     int rc = MTPT_OK;
     hipError_t e = hipSuccess;
     if (!rowcnt || !tmp || !bs || !drp) {
-        rc = fail(MTPT_E_NOMEM, "neighbour export allocation failed");
+        rc = fixed ? fail(MTPT_E_ARG, "neighbour export of %lld rows needs %zu bytes of scratch, more than the "
+                                      "static scratch's %zu", (long long)n, csr_scratch_bytes(n, 0), fixed_bytes)
+                   : fail(MTPT_E_NOMEM, "neighbour export allocation failed");
         goto done;
     }
     {
@@ -1015,9 +1059,12 @@ int csr_export(mtpt_sim* s, int64_t* row_ptr, int64_t* col, int64_t cap, int64_t
         const int64_t nnz = row_ptr[n];
         *nnz_out = nnz;
         if (col && nnz <= cap && nnz > 0) {
-            dcol = static_cast<int64_t*>(s->alloc.get(static_cast<size_t>(nnz) * 8));
+            dcol = static_cast<int64_t*>(sc.get(static_cast<size_t>(nnz) * 8));
             if (!dcol) {
-                rc = fail(MTPT_E_NOMEM, "neighbour export allocation failed");
+                rc = fixed ? fail(MTPT_E_ARG, "neighbour export of %lld entries needs %zu bytes of scratch, more "
+                                              "than the static scratch's %zu (row_ptr is written)",
+                                  (long long)nnz, csr_scratch_bytes(n, nnz), fixed_bytes)
+                           : fail(MTPT_E_NOMEM, "neighbour export allocation failed");
                 goto done;
             }
             e = fill(drp, dcol);
@@ -1031,12 +1078,48 @@ int csr_export(mtpt_sim* s, int64_t* row_ptr, int64_t* col, int64_t cap, int64_t
     }
 done:
     (void)hipStreamSynchronize(s->stream);
-    s->alloc.put(rowcnt);
-    s->alloc.put(tmp);
-    s->alloc.put(bs);
-    s->alloc.put(drp);
-    s->alloc.put(dcol);
+    sc.put(rowcnt);
+    sc.put(tmp);
+    sc.put(bs);
+    sc.put(drp);
+    sc.put(dcol);
     return rc;
+}
+
+// ------------------------------------------------------------ static scratch
+// Device scratch of mtpt_neighbors_static: one file-scope array, of which
+// every GPU the library runs on holds its own copy until the process ends.
+// Host code never uses the array's name except to look its address up:
+// hipGetSymbolAddress, once per device with that device current; the
+// address is kept per device and passed to the kernels like any buffer.
+constexpr size_t kStaticScratchBytes = static_cast<size_t>(64) << 20;
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// This device's address of the array (device: the sim's device).
+int static_scratch(int device, char** out)
+{
+    if (device < 0 || device >= kMaxDevices)
+        return fail(MTPT_E_DEVICE, "device %d beyond the static scratch's table", device);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        int cur = 0;
+        HIP_TRY(hipGetDevice(&cur));
+        if (cur != device)
+            HIP_TRY(hipSetDevice(device));
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (cur != device)
+            (void)hipSetDevice(cur);
+        if (e != hipSuccess || !p)
+            return fail(MTPT_E_DEVICE, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+        g_scratch_ptr[device] = p;
+    }
+    *out = static_cast<char*>(g_scratch_ptr[device]);
+    return MTPT_OK;
 }
 
 hipError_t export_pass(const mtpt_sim* s, int ph, const SimArgs& a)
@@ -1068,6 +1151,32 @@ int mtpt_neighbors(mtpt_sim* s, int64_t* row_ptr, int64_t* col, int64_t cap, int
         s, row_ptr, col, cap, nnz_out,
         [&](uint32_t* rowcnt) { return launch_nb_count(dim, prec, a, pid, rowcnt, s->stream); },
         [&](const int64_t* drp, int64_t* dcol) { return launch_nb_fill(dim, prec, a, pid, drp, dcol, s->stream); });
+}
+
+int mtpt_neighbors_static(mtpt_sim* s, int64_t* row_ptr, int64_t* col, int64_t cap, int64_t* nnz_out)
+{
+    if (!s || !row_ptr || !nnz_out)
+        return fail(MTPT_E_ARG, "NULL argument");
+    row_ptr[0] = 0;
+    *nnz_out = 0;
+    if (s->q.n == 0)
+        return MTPT_OK;
+    if (csr_scratch_bytes(s->q.n, 0) > kStaticScratchBytes)
+        return fail(MTPT_E_ARG, "neighbour export of %lld rows needs %zu bytes of scratch, more than the "
+                                "static scratch's %zu", (long long)s->q.n, csr_scratch_bytes(s->q.n, 0),
+                    kStaticScratchBytes);
+    char* base = nullptr;
+    const int rc = static_scratch(s->device, &base);
+    if (rc)
+        return rc;
+    const SimArgs a = base_args(s);
+    const int dim = s->q.dim, prec = s->q.prec;
+    const uint32_t* pid = cur_pid(s);
+    return csr_export(
+        s, row_ptr, col, cap, nnz_out,
+        [&](uint32_t* rowcnt) { return launch_nb_count(dim, prec, a, pid, rowcnt, s->stream); },
+        [&](const int64_t* drp, int64_t* dcol) { return launch_nb_fill(dim, prec, a, pid, drp, dcol, s->stream); },
+        base, kStaticScratchBytes);
 }
 
 int mtpt_step_neighbors(mtpt_sim* s, int32_t which, int64_t* row_ptr, int64_t* col, int64_t cap,

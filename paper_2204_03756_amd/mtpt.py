@@ -87,6 +87,7 @@ def load():
         "mtpt_stats": (C.c_int, [C.c_void_p, P(mtpt_stats_t)]),
         "mtpt_neighbors": (C.c_int, [C.c_void_p, _i64p, _i64p, C.c_int64, _i64p]),
         "mtpt_step_neighbors": (C.c_int, [C.c_void_p, C.c_int32, _i64p, _i64p, C.c_int64, _i64p]),
+        "mtpt_neighbors_static": (C.c_int, [C.c_void_p, _i64p, _i64p, C.c_int64, _i64p]),
         "mtpt_destroy": (C.c_int, [C.c_void_p]),
         "mtpt_last_error": (C.c_char_p, []),
         "mtpt_abi_version": (C.c_int, []),
