@@ -401,6 +401,37 @@ __device__ __forceinline__ V block_sum(V v)
     return t;
 }
 
+// N workgroup sums at once, each in the order of block_sum (wave shuffle
+// tree, then the waves in order); results valid in thread 0.  One barrier
+// for all N (the caller's last use of the workgroup, so none after it).
+template <int NT, int N, typename V>
+__device__ __forceinline__ void block_sum_n_final(V* v)
+{
+    __shared__ V red[N][NT / 64];
+    const int lane = threadIdx.x & 63;
+    const int wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < N; ++q) {
+        V x = v[q];
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1)
+            x += __shfl_down(x, off, 64);
+        if (lane == 0)
+            red[q][wid] = x;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int q = 0; q < N; ++q) {
+            V t = V(0);
+#pragma unroll
+            for (int w = 0; w < NT / 64; ++w)
+                t += red[q][w];
+            v[q] = t;
+        }
+    }
+}
+
 // Workgroups are dispatched to the 8 XCDs round-robin (workgroup b on XCD
 // b mod 8), each XCD with its own L2.  Remapping b so that every XCD runs one
 // contiguous chunk of logical blocks keeps neighbouring tiles and slot ranges,
@@ -764,9 +795,11 @@ __device__ __forceinline__ void scan_row(const SimArgs& a, PX p, PS sr, PM ms, u
 // its slot from the tile's LDS histogram hist (two 16-bit counts per word,
 // used when the tile holds fewer than 65536 particles: tile_hist); one that
 // leaves takes it from the global histogram, flagged in bit 31 of its rank.
+// The slot is returned, not stored: the caller stores it after other work,
+// so that the atomic's round trip overlaps that work.
 template <int D, typename T>
-__device__ __forceinline__ void bin_next(const SimArgs& a, uint32_t i, const T* x, const T* jump, const int* tlo,
-                                         const int* thi, uint32_t* hist, bool tile_hist)
+__device__ __forceinline__ uint32_t bin_next(const SimArgs& a, uint32_t i, const T* x, const T* jump,
+                                             const int* tlo, const int* thi, uint32_t* hist, bool tile_hist)
 {
     uint32_t c = 0, lc = 0;
     bool inside = true;
@@ -787,7 +820,7 @@ __device__ __forceinline__ void bin_next(const SimArgs& a, uint32_t i, const T* 
     } else {
         rank = 0x80000000u | atomicAdd(&a.counts[c], 1u);
     }
-    a.rank[i] = rank;
+    return rank;
 }
 
 // One tile: tx * ty * tz cells (tz = 1 in 2-d).  Halo rows (cells xa..xb-1
@@ -811,6 +844,12 @@ __device__ __forceinline__ void tile_body(const SimArgs& a, uint32_t blk)
     // rows are trimmed to the spherical cutoff's x-window; an ellipsoidal
     // cutoff scans its rows whole (the host never sets trim_rows for it)
     constexpr bool kTrim = !TN;
+    // the FP64 row-sum pass evaluates its (software) exp only for the
+    // candidates within the cutoff, after each chunk of 32, where rows are
+    // not trimmed (about one candidate in six is in; in trimmed rows most
+    // are, and the second loop costs more than it saves: measured)
+    constexpr bool kExpAfter = !TRANSFER && PREC == 0;
+    const bool exp_after = kExpAfter && !(kTrim && a.trim_rows);
     __shared__ T lpos[D][CAP];
     __shared__ T lsr[SCAP];
     __shared__ M lms[NS][SCAP];
@@ -868,17 +907,34 @@ __device__ __forceinline__ void tile_body(const SimArgs& a, uint32_t blk)
 
     // every cell boundary of the halo rows in one round of loads, as global
     // slots (a row outside the grid is empty); the runs of the halo rows and
-    // of the own rows follow from it
+    // of the own rows follow from it.  A thread issues all its loads before
+    // its first LDS store, so that they are in flight together (one round
+    // trip instead of one per entry: measured 3.8 -> ~1.5 us of a 3-d tile).
     const int ncb = ncol + 1;
-    for (int idx = tid; idx < nseg * ncb; idx += kBlock) {
-        const int sg = idx / ncb;
-        const int c = idx - sg * ncb;
-        const int pz = D == 3 ? z0 - 1 + sg / rows : 0;
-        const int py = y0 - 1 + sg % rows;
-        uint32_t v = 0;
-        if (py >= 0 && py < nc1 && pz >= 0 && pz < nc2)
-            v = a.starts[(static_cast<uint32_t>(pz) * nc1 + py) * nc0 + xa + c];
-        cst[sg][c] = v;
+    {
+        constexpr int kCstIt = (kSegs * TileLimits<D>::cols + kBlock - 1) / kBlock;
+        uint32_t cv[kCstIt];
+#pragma unroll
+        for (int it = 0; it < kCstIt; ++it) {
+            const int idx = tid + it * kBlock;
+            cv[it] = 0;
+            if (idx < nseg * ncb) {
+                const int sg = idx / ncb;
+                const int c = idx - sg * ncb;
+                const int pz = D == 3 ? z0 - 1 + sg / rows : 0;
+                const int py = y0 - 1 + sg % rows;
+                if (py >= 0 && py < nc1 && pz >= 0 && pz < nc2)
+                    cv[it] = a.starts[(static_cast<uint32_t>(pz) * nc1 + py) * nc0 + xa + c];
+            }
+        }
+#pragma unroll
+        for (int it = 0; it < kCstIt; ++it) {
+            const int idx = tid + it * kBlock;
+            if (idx < nseg * ncb) {
+                const int sg = idx / ncb;
+                cst[sg][idx - sg * ncb] = cv[it];
+            }
+        }
     }
     __syncthreads();
     uint32_t slen = 0;
@@ -1058,8 +1114,9 @@ __device__ __forceinline__ void tile_body(const SimArgs& a, uint32_t blk)
             }
         }
         const uint32_t i = own_gb[r] + (tt - own_pre[r]);
-        // the particle's LDS slot; its own position from there when the lanes
-        // are permuted (cell order), else a coalesced global load
+        // the particle's LDS slot; its own position (and, in the transfer
+        // pass, row sum and masses) from there when the tile is staged, else
+        // coalesced global loads
         const int smid0 = srow(r);
         const uint32_t lself = i - seg_gb[smid0] + seg_off[smid0];
         // first halo row of the particle's lowest candidate plane
@@ -1067,7 +1124,7 @@ __device__ __forceinline__ void tile_body(const SimArgs& a, uint32_t blk)
         T xi[3];
 #pragma unroll
         for (int d = 0; d < D; ++d)
-            xi[d] = cell_order ? lpos[d][lself] : static_cast<const T*>(a.x[d])[i];
+            xi[d] = use_lds ? lpos[d][lself] : static_cast<const T*>(a.x[d])[i];
         const int cxr = cell_coord(static_cast<double>(xi[0]), a.glo[0], a.inv_side[0], nc0) - xa;
         const int cl = cxr > 0 ? cxr - 1 : 0;
         const int ch = cxr + 2 < ncol ? cxr + 2 : ncol;
@@ -1091,21 +1148,21 @@ __device__ __forceinline__ void tile_body(const SimArgs& a, uint32_t blk)
                 ++ecnt;
             }
         };
-        // the particle's jumps and neighbour masks are loaded with its row
-        // sum and masses (issued later, they would wait behind the stores
-        // that precede their use), except in the 3-d three-species pass,
-        // whose registers are the tighter limit
-        constexpr bool kEarly = TRANSFER && !(D == 3 && NS == 3);
+        // the particle's jumps and neighbour masks are loaded before its
+        // candidate loops, all at once (issued later, each would stall the
+        // wave in front of its use: measured 10 % of the 3-d three-species
+        // transfer pass)
+        constexpr bool kEarly = TRANSFER;
         T jv[3] = {T(0), T(0), T(0)};
         uint64_t mkp[planes], wkp[planes];
 #pragma unroll
         for (int pzr = 0; pzr < planes; ++pzr)
             mkp[pzr] = wkp[pzr] = 0ull;
         if constexpr (TRANSFER) {
-            acc.si = static_cast<const T*>(a.srow)[i];
+            acc.si = use_lds ? lsr[lself < SCAP ? lself : 0] : static_cast<const T*>(a.srow)[i];
 #pragma unroll
             for (int c = 0; c < NS; ++c) {
-                acc.mi[c] = static_cast<const M*>(a.m_mid[c])[i];
+                acc.mi[c] = use_lds ? lms[c][lself < SCAP ? lself : 0] : static_cast<const M*>(a.m_mid[c])[i];
                 acc.dl[c] = 0;
                 acc.comp[c] = 0;
             }
@@ -1267,10 +1324,15 @@ __device__ __forceinline__ void tile_body(const SimArgs& a, uint32_t blk)
                             record(seg_gb[sgi] + (lidx - seg_off[sgi]));
                         }
                     }
-                    const T kv = Pair<D, T>::kernel(a, r2);
                     if constexpr (!TRANSFER) {
-                        acc.s += in ? kv : T(0);
+                        // the FP64 pass sums its kernel values after each
+                        // chunk, over the chunk's neighbours only
+                        if (!exp_after) {
+                            const T kv = Pair<D, T>::kernel(a, r2);
+                            acc.s += in ? kv : T(0);
+                        }
                     } else {
+                        const T kv = Pair<D, T>::kernel(a, r2);
                         using A = typename Types<PREC>::A;
                         const T w = Pair<D, T>::weight(kv, acc.si, ld(lsr, off));
 #pragma unroll
@@ -1356,6 +1418,29 @@ __device__ __forceinline__ void tile_body(const SimArgs& a, uint32_t blk)
                     if constexpr (!TRANSFER) {
                         // candidate k0 + j at bit j
                         mw = __builtin_bitreverse32(mw) >> (32u - (kend - k0));
+                        if (exp_after) {
+                            // kernel values of the chunk's candidates within
+                            // the cutoff (the particle itself included), in
+                            // candidate order: the same sum as adding every
+                            // candidate's value or zero, with the software
+                            // FP64 exp evaluated for about one candidate in
+                            // six instead of all
+                            uint32_t mr = mw;
+                            uint32_t rmax = static_cast<uint32_t>(__builtin_popcount(mr));
+                            rmax = wave_max_u32(rmax);
+                            for (uint32_t q = 0; q < rmax; ++q) {
+                                const bool valid = mr != 0u;
+                                const uint32_t kb = valid ? static_cast<uint32_t>(__builtin_ctz(mr)) : 0u;
+                                mr &= mr - 1u;
+                                const uint32_t off = slot_of(k0 + kb, valid);
+                                T xj[3];
+#pragma unroll
+                                for (int d = 0; d < D; ++d)
+                                    xj[d] = ld(lpos[d], off);
+                                const T kv = Pair<D, T>::kernel(a, Metric<D, T, TN>::r2(a, xi, xj));
+                                acc.s += valid ? kv : T(0);
+                            }
+                        }
                         // the particle itself is candidate l0 + (li - b1) of
                         // its own plane's middle row
                         if (pzr == planes / 2) {
@@ -1401,6 +1486,20 @@ __device__ __forceinline__ void tile_body(const SimArgs& a, uint32_t blk)
             static_cast<T*>(a.srow)[i] = acc.s;
             pairs += acc.cnt - 1u;
         } else {
+            // the next step's walk and binning first: the slot's atomic (for
+            // a particle that leaves the tile) is in flight during the mass
+            // update and the reaction
+            uint32_t nrank = 0;
+            if (a.fuse_bin) {
+                const int tlo[3] = {x0, y0, z0};
+                const int thi[3] = {x1, y1, z1};
+                if (!kEarly) {
+#pragma unroll
+                    for (int d = 0; d < D; ++d)
+                        jv[d] = static_cast<const T*>(a.jmp[d])[i];
+                }
+                nrank = bin_next<D, T>(a, i, xi, jv, tlo, thi, hist, own_total < 65536u);
+            }
             double mo[3];
 #pragma unroll
             for (int c = 0; c < NS; ++c) {
@@ -1419,16 +1518,8 @@ __device__ __forceinline__ void tile_body(const SimArgs& a, uint32_t blk)
                 static_cast<M*>(a.m_dst[c])[i] = st;
                 msum[c] += static_cast<double>(st);
             }
-            if (a.fuse_bin) {
-                const int tlo[3] = {x0, y0, z0};
-                const int thi[3] = {x1, y1, z1};
-                if (!kEarly) {
-#pragma unroll
-                    for (int d = 0; d < D; ++d)
-                        jv[d] = static_cast<const T*>(a.jmp[d])[i];
-                }
-                bin_next<D, T>(a, i, xi, jv, tlo, thi, hist, own_total < 65536u);
-            }
+            if (a.fuse_bin)
+                a.rank[i] = nrank;
         }
     }
     if constexpr (EXPORT)
@@ -1447,11 +1538,11 @@ __device__ __forceinline__ void tile_body(const SimArgs& a, uint32_t blk)
         if (tid == 0)
             a.pair_part[blk] = p;
     } else {
+        block_sum_n_final<kBlock, NS, double>(msum);
+        if (tid == 0) {
 #pragma unroll
-        for (int c = 0; c < NS; ++c) {
-            const double t = block_sum<kBlock, double>(msum[c]);
-            if (tid == 0)
-                a.partials[static_cast<size_t>(blk) * NS + c] = t;
+            for (int c = 0; c < NS; ++c)
+                a.partials[static_cast<size_t>(blk) * NS + c] = msum[c];
         }
     }
 }

@@ -68,6 +68,72 @@ def test_pool_alone_equals_mix(mt, oracle):
         assert err <= 1e-5
 
 
+def test_pool_large_requests_match_the_oracle(mt, oracle):
+    """Two large requests of the serving mix's shape -- a 2-d sim of ~1e6
+    particles and a 3-d one of ~3e5, 100 and 120 steps, Kahan FP32 -- run
+    together in the pool with small requests admitted around them: the
+    large results equal the oracle within the FP32 bar, and the small ones
+    equal their solo runs bit for bit."""
+    big = [W.request(101, n_min=9.0e5, n_max=1.0e6), W.request(102, n_min=2.9e5, n_max=3.0e5)]
+    big[0].steps, big[1].steps = 100, 120
+    small = [W.request(200 + i, n_min=1e4, n_max=3e4) for i in range(6)]
+    for r in small:
+        r.steps = min(r.steps, 40)
+    say = lambda *a: print(*a, flush=True)
+    say(f"  pool: large dims {[r.params.dim for r in big]} n {[r.params.n for r in big]}")
+    pool = mt.mtpt_pool_create(0, 4)
+    results = {}
+    try:
+        pending = big + small
+        active = {}
+        ticks = 0
+        while pending or active:
+            while pending:
+                r = pending[0]
+                t = mt.mtpt_pool_admit(pool, r.params, r.x0, r.m0, r.steps)
+                if t is None:
+                    break
+                active[t] = r
+                pending.pop(0)
+            mt.mtpt_pool_tick(pool)
+            ticks += 1
+            for t in list(active):
+                if mt.mtpt_pool_done(pool, t):
+                    r = active.pop(t)
+                    results[r.rid] = mt.mtpt_pool_result(pool, t, r.params.n, 1)
+        say(f"  pool: {len(results)} sims in {ticks} ticks")
+    finally:
+        mt.mtpt_pool_destroy(pool)
+    for r in big:
+        ref = oracle.run(r.params, r.x0, r.m0, r.steps)
+        err = np.max(np.abs(results[r.rid] - ref.m)) / np.max(np.abs(ref.m))
+        say(f"  pool large request {r.rid}: normwise {err:.3e}")
+        assert err <= 1e-5
+    for r in small:
+        assert np.array_equal(alone(mt, r), results[r.rid])
+
+
+def test_sim_bytes_equal_the_allocation(mt):
+    """mtpt_sim_bytes (the admission estimate) equals what create allocates,
+    also with a rotated dispersion tensor (cells stretched per axis)."""
+    class Counting(mt.TorchAllocator):
+        def __init__(self):
+            super().__init__("cuda:0")
+            self.sizes = []
+
+        def _alloc(self, nbytes, ctx):
+            self.sizes.append(int(nbytes))
+            return super()._alloc(nbytes, ctx)
+    for w in (W.rw2d(n=50_000), W.aniso2d(n=50_000),
+              W.Workload("t3", W.replace(W.react3d(n=60_000).params,
+                                         disp=W.rotated_tensor([3.0, 1.0, 0.5], [0.3, 0.2, 0.1])),
+                         W.react3d(n=60_000).x0, W.react3d(n=60_000).m0, 1, {})):
+        alloc = Counting()
+        sim = mt.Sim(w.params, w.x0, w.m0, allocator=alloc)
+        sim.close()
+        assert alloc.sizes[0] == mt.mtpt_sim_bytes(w.params), w.name
+
+
 def test_pool_admission_budget_and_slots(mt):
     r = W.request(3, n_min=5e3, n_max=6e3)
     need = mt.mtpt_sim_bytes(r.params)
