@@ -319,6 +319,15 @@ template <> struct Window<float> {
     }
 };
 
+// v / d for 0 <= v < 4096 and 1 <= d <= 256, with inv = 1.0f / d: the exact
+// quotient plus (v mod d + 0.5) / d lies at least 0.5 / d >= 2^-9 from an
+// integer, and the FP32 product is off by less than 4096 * 2^-22 = 2^-10, so
+// the truncation is exact (no integer divide sequence)
+__device__ __forceinline__ int small_div(int v, float inv)
+{
+    return static_cast<int>((static_cast<float>(v) + 0.5f) * inv);
+}
+
 // Wave64 primitives on DPP lane moves (no LDS round trip).  Every lane of
 // the wave must be active.
 // one DPP move: lane value from the lane that dpp_ctrl selects, 0 where that
@@ -696,8 +705,11 @@ __device__ __forceinline__ void react3(double* m, const SimArgs& a)
         cb = t;
     }
     const double d = ca - cb;
-    const double an = d > 0.0 ? ca * d / (d - cb * expm1(-a.k_react * d * a.dt))
-                              : ca / (1.0 + a.k_react * ca * a.dt);
+    // one division for both cases (operands chosen first)
+    const bool dpos = d > 0.0;
+    const double num = dpos ? ca * d : ca;
+    const double den = dpos ? d - cb * expm1(-a.k_react * d * a.dt) : 1.0 + a.k_react * ca * a.dt;
+    const double an = num / den;
     const double bn = an - d;
     const double reacted = ca - an;
     m[0] = (sw ? bn : an) * a.to_m;
@@ -810,7 +822,8 @@ __device__ __forceinline__ uint32_t bin_next(const SimArgs& a, uint32_t i, const
         const int ck = cell_coord(static_cast<double>(v), a.glo[k], a.inv_side[k], a.nc[k]);
         c = c * static_cast<uint32_t>(a.nc[k]) + static_cast<uint32_t>(ck);
         inside = inside && ck >= tlo[k] && ck < thi[k];
-        lc = lc * static_cast<uint32_t>(thi[k] - tlo[k]) + static_cast<uint32_t>(ck - tlo[k]);
+        // tile-local index < 2^16 (a 24-bit multiply)
+        lc = __umul24(lc, static_cast<uint32_t>(thi[k] - tlo[k])) + static_cast<uint32_t>(ck - tlo[k]);
     }
     a.cell[i] = c;
     uint32_t rank;
@@ -826,9 +839,9 @@ __device__ __forceinline__ uint32_t bin_next(const SimArgs& a, uint32_t i, const
 // One tile: tx * ty * tz cells (tz = 1 in 2-d).  Halo rows (cells xa..xb-1
 // of rows y0-1..y1 of planes z0-1..z1) are staged in LDS with the offsets of
 // their cell boundaries; a particle in cell cx visits cells cx-1..cx+1 of
-// each of its 3^(d-1) neighbouring rows, restricted to the x-window.  The
-// tile's own rows are numbered y fastest: own row r is row r % nrow of own
-// plane r / nrow.
+// each of its 3^(d-1) neighbouring rows, restricted to the x-window.  Halo
+// and own rows are numbered y fastest with a fixed pitch per plane (see
+// TileLimits); rows past the tile's extent are empty.
 // With EXPORT the pass changes nothing: it records, for every own particle,
 // the pairs it would use -- a.nb_col == nullptr: their count plus one (self)
 // into a.nb_cnt[pid]; else the pids, self first, into a.nb_col from
@@ -854,7 +867,8 @@ __device__ __forceinline__ void tile_body(const SimArgs& a, uint32_t blk)
     __shared__ T lsr[SCAP];
     __shared__ M lms[NS][SCAP];
     constexpr int kSegs = TileLimits<D>::segs;
-    constexpr int kRows = TileLimits<D>::max_y * TileLimits<D>::max_z;   // own rows
+    constexpr int kRows = TileLimits<D>::own_rows;   // own rows (pitch kSY per plane)
+    constexpr int kSY = TileLimits<D>::seg_y;
     __shared__ uint32_t seg_gb[kSegs];
     __shared__ uint32_t seg_off[kSegs + 1];
     __shared__ uint32_t cst[kSegs][TileLimits<D>::cols];
@@ -875,7 +889,8 @@ __device__ __forceinline__ void tile_body(const SimArgs& a, uint32_t blk)
     __shared__ uint32_t obase[64];
     // per-cell counts of the particles that stay in the tile, two 16-bit
     // counts per word
-    constexpr int kHist = TRANSFER ? (TileLimits<D>::max_x * kRows + 1) / 2 : 1;
+    constexpr int kHist =
+        TRANSFER ? (TileLimits<D>::max_x * TileLimits<D>::max_y * TileLimits<D>::max_z + 1) / 2 : 1;
     __shared__ uint32_t hist[kHist];
 
     const int tid = threadIdx.x;
@@ -892,11 +907,15 @@ __device__ __forceinline__ void tile_body(const SimArgs& a, uint32_t blk)
     const int z0 = D == 3 ? tzi * a.tile[2] : 0;
     const int z1 = D == 3 ? min(z0 + a.tile[2], nc2) : 1;
     const int nrow = y1 - y0;                      // own rows per own plane
-    const int nown = nrow * (z1 - z0);             // own rows
+    const int nz = z1 - z0;                        // own planes (1 in 2-d)
+    const int nown = nrow * nz;                    // own rows
     const int rows = nrow + 2;                     // halo rows per halo plane
-    const int nseg = rows * (D == 3 ? z1 - z0 + 2 : 1);
-    // halo row of own row r
-    auto srow = [nrow, rows](int r) { return D == 3 ? (r / nrow + 1) * rows + r % nrow + 1 : r + 1; };
+    // Halo row sg = pz * kSY + py holds cells xa..xb-1 of grid row y0 - 1 + py
+    // of plane z0 - 1 + pz (py < rows, pz < nz + 2; the others are empty).
+    // Own row r = rz * kSY + ry holds cells x0..x1-1 of row y0 + ry of plane
+    // z0 + rz (ry < nrow, rz < nz); its halo row is srow(r), and the halo rows
+    // of its lowest candidate plane start at r.
+    auto srow = [](int r) { return D == 3 ? r + kSY + 1 : r + 1; };
     const int xa = x0 > 0 ? x0 - 1 : 0;
     const int xb = x1 < nc0 ? x1 + 1 : nc0;
     const int ncol = xb - xa;
@@ -911,74 +930,83 @@ __device__ __forceinline__ void tile_body(const SimArgs& a, uint32_t blk)
     // its first LDS store, so that they are in flight together (one round
     // trip instead of one per entry: measured 3.8 -> ~1.5 us of a 3-d tile).
     const int ncb = ncol + 1;
-    {
-        constexpr int kCstIt = (kSegs * TileLimits<D>::cols + kBlock - 1) / kBlock;
-        uint32_t cv[kCstIt];
+    // Thread k of a round takes boundary c = k % kCP of halo row k / kCP (a
+    // power-of-two pitch: no integer division).  The loaded global slots stay
+    // in registers until the rows' LDS offsets are known, then are stored
+    // converted (kept as global slots when the tile does not fit the LDS).
+    constexpr int kCP = TileLimits<D>::col_p;
+    constexpr int kCstIt = (kSegs * kCP + kBlock - 1) / kBlock;
+    uint32_t cv[kCstIt];
 #pragma unroll
-        for (int it = 0; it < kCstIt; ++it) {
-            const int idx = tid + it * kBlock;
-            cv[it] = 0;
-            if (idx < nseg * ncb) {
-                const int sg = idx / ncb;
-                const int c = idx - sg * ncb;
-                const int pz = D == 3 ? z0 - 1 + sg / rows : 0;
-                const int py = y0 - 1 + sg % rows;
-                if (py >= 0 && py < nc1 && pz >= 0 && pz < nc2)
-                    cv[it] = a.starts[(static_cast<uint32_t>(pz) * nc1 + py) * nc0 + xa + c];
-            }
-        }
+    for (int it = 0; it < kCstIt; ++it) {
+        const int idx = tid + it * kBlock;
+        const int sg = idx / kCP;
+        const int c = idx % kCP;
+        const int pzr = D == 3 ? sg / kSY : 0;
+        const int pyr = D == 3 ? sg % kSY : sg;
+        const int pz = z0 - 1 + pzr;
+        const int py = y0 - 1 + pyr;
+        const bool in = sg < kSegs && c < ncb && pyr < rows && (D == 2 || pzr < nz + 2) && py >= 0 &&
+                        py < nc1 && (D == 2 || (pz >= 0 && pz < nc2));
+        cv[it] = in ? a.starts[(static_cast<uint32_t>(D == 3 ? pz : 0) * nc1 + py) * nc0 + xa + c] : 0u;
+    }
 #pragma unroll
-        for (int it = 0; it < kCstIt; ++it) {
-            const int idx = tid + it * kBlock;
-            if (idx < nseg * ncb) {
-                const int sg = idx / ncb;
-                cst[sg][idx - sg * ncb] = cv[it];
-            }
-        }
+    for (int it = 0; it < kCstIt; ++it) {
+        const int idx = tid + it * kBlock;
+        if (idx / kCP < kSegs && idx % kCP < ncb)
+            cst[idx / kCP][idx % kCP] = cv[it];
     }
     __syncthreads();
     uint32_t slen = 0;
-    if (tid < nseg) {
+    if (tid < kSegs) {
         seg_gb[tid] = cst[tid][0];
         slen = cst[tid][ncol] - cst[tid][0];
     }
     uint32_t total;
     const uint32_t soff = block_excl_scan(slen, &total);
-    if (tid < nseg)
+    if (tid < kSegs)
         seg_off[tid] = soff;
     if (tid == 0)
-        seg_off[nseg] = total;
+        seg_off[kSegs] = total;
     uint32_t olen = 0;
-    if (tid < nown) {
-        const int sr = srow(tid);
-        const uint32_t gb = cst[sr][x0 - xa];
-        olen = cst[sr][x1 - xa] - gb;
+    if (tid < kRows) {
+        const int ry = D == 3 ? tid % kSY : tid;
+        const int rz = D == 3 ? tid / kSY : 0;
+        uint32_t gb = 0;
+        if (ry < nrow && rz < nz) {
+            const int sr = srow(tid);
+            gb = cst[sr][x0 - xa];
+            olen = cst[sr][x1 - xa] - gb;
+        }
         own_gb[tid] = gb;
     }
     uint32_t own_total;
     const uint32_t ooff = block_excl_scan(olen, &own_total);
-    if (tid < nown)
+    if (tid < kRows)
         own_pre[tid] = ooff;
     if (tid == 0)
-        own_pre[nown] = own_total;
+        own_pre[kRows] = own_total;
     __syncthreads();
 
     const bool use_lds = total <= static_cast<uint32_t>(CAP);
     // the row-sum pass (one-species instantiation) staged this tile in LDS
     // too, so it recorded the neighbour masks
     const bool mask_ok = total <= static_cast<uint32_t>(TileCap<D, PREC, 1, false>::value);
-    // cell boundaries of every halo row as LDS offsets (kept as global slots
-    // when the tile does not fit)
-    if (use_lds)
-        for (int idx = tid; idx < nseg * ncb; idx += kBlock) {
-            const int sg = idx / ncb;
-            const int c = idx - sg * ncb;
-            cst[sg][c] = cst[sg][c] - seg_gb[sg] + seg_off[sg];
+    // cell boundaries of every halo row as LDS offsets (read by the particle
+    // loop after the staging barrier)
+    if (use_lds) {
+#pragma unroll
+        for (int it = 0; it < kCstIt; ++it) {
+            const int idx = tid + it * kBlock;
+            const int sg = idx / kCP;
+            if (sg < kSegs && idx % kCP < ncb)
+                cst[sg][idx % kCP] = cv[it] - seg_gb[sg] + seg_off[sg];
         }
-    // own row of every own particle, when they fit the table
+    }
+    // own row of every own particle, when they fit the table (2-d)
     const bool rows_tab = kRowTab && own_total <= static_cast<uint32_t>(CAP);
     if (rows_tab)
-        for (int r = tid >> 6; r < nown; r += kBlock / 64)
+        for (int r = tid >> 6; r < kRows; r += kBlock / 64)
             for (uint32_t j = static_cast<uint32_t>(tid & 63); j < own_pre[r + 1] - own_pre[r]; j += 64)
                 row_of[own_pre[r] + j] = static_cast<uint8_t>(r);
     if (use_lds) {
@@ -994,9 +1022,11 @@ __device__ __forceinline__ void tile_body(const SimArgs& a, uint32_t blk)
             sidx[it] = static_cast<uint32_t>(tid + it * kBlock);
             sb[it] = 0;
         }
-        // last row whose first slot is <= the slot (seg_off[0] = 0); the
-        // range [sb, sb + len) always holds it
-        for (int len = nseg; len > 1;) {
+        // last row whose first slot is <= the slot (seg_off[0] = 0; an empty
+        // row shares its offset with the next one, which then wins); the range
+        // [sb, sb + len) always holds it
+#pragma unroll
+        for (int len = kSegs; len > 1;) {
             const int half = len >> 1;
 #pragma unroll
             for (int it = 0; it < kIt; ++it)
@@ -1104,27 +1134,35 @@ __device__ __forceinline__ void tile_body(const SimArgs& a, uint32_t blk)
         if (rows_tab) {
             r = row_of[kRowTab ? tt : 0u];
         } else {
-            int hi = nown - 1;
-            while (r < hi) {
-                const int mid = (r + hi + 1) >> 1;
-                if (own_pre[mid] <= tt)
-                    r = mid;
-                else
-                    hi = mid - 1;
+            // last own row whose first particle is <= tt (an empty row shares
+            // its offset with the next one, which then wins), in fixed steps
+#pragma unroll
+            for (int len = kRows; len > 1;) {
+                const int half = len >> 1;
+                r = own_pre[r + half] <= tt ? r + half : r;
+                len -= half;
             }
         }
         const uint32_t i = own_gb[r] + (tt - own_pre[r]);
         // the particle's LDS slot; its own position (and, in the transfer
         // pass, row sum and masses) from there when the tile is staged, else
-        // coalesced global loads
+        // coalesced global loads (LDS reads and global loads stay separate
+        // instructions: a select of the two addresses would make them flat
+        // loads)
         const int smid0 = srow(r);
         const uint32_t lself = i - seg_gb[smid0] + seg_off[smid0];
+        const uint32_t lq = use_lds ? lself : 0u;
         // first halo row of the particle's lowest candidate plane
-        const int rbase = D == 3 ? (r / nrow) * rows + r % nrow : r;
+        const int rbase = r;
         T xi[3];
 #pragma unroll
         for (int d = 0; d < D; ++d)
-            xi[d] = use_lds ? lpos[d][lself] : static_cast<const T*>(a.x[d])[i];
+            xi[d] = lpos[d][lq];
+        if (!use_lds) {
+#pragma unroll
+            for (int d = 0; d < D; ++d)
+                xi[d] = static_cast<const T*>(a.x[d])[i];
+        }
         const int cxr = cell_coord(static_cast<double>(xi[0]), a.glo[0], a.inv_side[0], nc0) - xa;
         const int cl = cxr > 0 ? cxr - 1 : 0;
         const int ch = cxr + 2 < ncol ? cxr + 2 : ncol;
@@ -1159,12 +1197,19 @@ __device__ __forceinline__ void tile_body(const SimArgs& a, uint32_t blk)
         for (int pzr = 0; pzr < planes; ++pzr)
             mkp[pzr] = wkp[pzr] = 0ull;
         if constexpr (TRANSFER) {
-            acc.si = use_lds ? lsr[lself < SCAP ? lself : 0] : static_cast<const T*>(a.srow)[i];
+            const uint32_t ls = lq < SCAP ? lq : 0u;
+            acc.si = lsr[ls];
 #pragma unroll
             for (int c = 0; c < NS; ++c) {
-                acc.mi[c] = use_lds ? lms[c][lself < SCAP ? lself : 0] : static_cast<const M*>(a.m_mid[c])[i];
+                acc.mi[c] = lms[c][ls];
                 acc.dl[c] = 0;
                 acc.comp[c] = 0;
+            }
+            if (!use_lds) {
+                acc.si = static_cast<const T*>(a.srow)[i];
+#pragma unroll
+                for (int c = 0; c < NS; ++c)
+                    acc.mi[c] = static_cast<const M*>(a.m_mid[c])[i];
             }
             if (kEarly && a.fuse_bin) {
 #pragma unroll
@@ -1205,7 +1250,7 @@ __device__ __forceinline__ void tile_body(const SimArgs& a, uint32_t blk)
             }
 #pragma unroll
             for (int pzr = 0; pzr < planes; ++pzr) {
-                const int s0 = rbase + pzr * rows;
+                const int s0 = rbase + pzr * kSY;
                 uint32_t b0 = cst[s0][cl], l0 = cst[s0][ch] - b0;
                 uint32_t b1 = cst[s0 + 1][cl], l1 = cst[s0 + 1][ch] - b1;
                 uint32_t b2 = cst[s0 + 2][cl], l2 = cst[s0 + 2][ch] - b2;
@@ -1310,7 +1355,8 @@ __device__ __forceinline__ void tile_body(const SimArgs& a, uint32_t blk)
                 };
                 uint32_t kmax = tot;
                 kmax = wave_max_u32(kmax);
-                constexpr int kUnroll = D == 3 ? MTPT_CAND_UNROLL_3D : (PREC == 0 ? MTPT_CAND_UNROLL_2D_F64 : MTPT_CAND_UNROLL_2D);
+                constexpr int kUnroll = D == 3 ? (TRANSFER && NS == 3 ? MTPT_CAND_UNROLL_3D_S3 : MTPT_CAND_UNROLL_3D)
+                                               : (PREC == 0 ? MTPT_CAND_UNROLL_2D_F64 : MTPT_CAND_UNROLL_2D);
                 // one candidate at LDS byte offset off (of the T arrays), pair
                 // counted when in
                 auto visit = [&](uint32_t off, bool in, T r2) {
@@ -1319,7 +1365,7 @@ __device__ __forceinline__ void tile_body(const SimArgs& a, uint32_t blk)
                         if (in && off != obs && act) {
                             const uint32_t lidx = off / kT;
                             int sgi = 0;
-                            for (int q = 1; q < nseg; ++q)
+                            for (int q = 1; q < kSegs; ++q)
                                 sgi = seg_off[q] <= lidx ? q : sgi;
                             record(seg_gb[sgi] + (lidx - seg_off[sgi]));
                         }
@@ -1460,7 +1506,7 @@ __device__ __forceinline__ void tile_body(const SimArgs& a, uint32_t blk)
             for (int pzr = 0; pzr < planes; ++pzr) {
 #pragma unroll
                 for (int dy = 0; dy < 3; ++dy) {
-                    const int sg = rbase + pzr * rows + dy;
+                    const int sg = rbase + pzr * kSY + dy;
                     const uint32_t b = cst[sg][cl];
                     const uint32_t e = act ? cst[sg][ch] : b;
                     T xlo, xhi;
@@ -1527,9 +1573,12 @@ __device__ __forceinline__ void tile_body(const SimArgs& a, uint32_t blk)
     if (TRANSFER && a.fuse_bin) {
         // counts of the tile's cells from the particles that stayed in it
         __syncthreads();
+        const float inv_tw = 1.0f / static_cast<float>(tw);
+        const float inv_nrow = 1.0f / static_cast<float>(nrow);
         for (int k = tid; k < tw * nown; k += kBlock) {
-            const int rr = k / tw;   // own row, y fastest
-            const uint32_t c = (static_cast<uint32_t>(z0 + rr / nrow) * nc1 + (y0 + rr % nrow)) * nc0 + x0 + (k - rr * tw);
+            const int rr = small_div(k, inv_tw);   // own row, y fastest (dense)
+            const int rz = small_div(rr, inv_nrow);
+            const uint32_t c = (static_cast<uint32_t>(z0 + rz) * nc1 + (y0 + rr - rz * nrow)) * nc0 + x0 + (k - rr * tw);
             a.tcounts[c] = (hist[k >> 1] >> ((k & 1) << 4)) & 0xFFFFu;
         }
     }

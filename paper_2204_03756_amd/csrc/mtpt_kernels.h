@@ -58,9 +58,14 @@ constexpr uint32_t kScanFold = 2048;  // scans of at most this many tiles skip t
 #ifndef MTPT_LDS_BUDGET_3D_WIDE
 #define MTPT_LDS_BUDGET_3D_WIDE 46080
 #endif
+// 3-d three-species FP32-position passes
+#ifndef MTPT_LDS_BUDGET_3D_S3
+#define MTPT_LDS_BUDGET_3D_S3 46080
+#endif
 template <int D, int PREC, int NS> struct LdsBudget {
-    static constexpr int value = D == 3 ? (PREC != 0 && NS == 1 ? MTPT_LDS_BUDGET_3D : MTPT_LDS_BUDGET_3D_WIDE)
-                                        : (PREC == 0 ? MTPT_LDS_BUDGET_2D_F64 : MTPT_LDS_BUDGET_2D);
+    static constexpr int value =
+        D == 3 ? (PREC != 0 ? (NS == 1 ? MTPT_LDS_BUDGET_3D : MTPT_LDS_BUDGET_3D_S3) : MTPT_LDS_BUDGET_3D_WIDE)
+               : (PREC == 0 ? MTPT_LDS_BUDGET_2D_F64 : MTPT_LDS_BUDGET_2D);
 };
 // 3-d tiled passes keep a table of each own particle's row (else a search)
 #ifndef MTPT_ROW_TABLE_3D
@@ -85,15 +90,28 @@ template <int D, int PREC, int NS> struct LdsBudget {
 #ifndef MTPT_CAND_UNROLL_3D
 #define MTPT_CAND_UNROLL_3D 4
 #endif
+// the 3-d three-species transfer pass (registers: its occupancy level)
+#ifndef MTPT_CAND_UNROLL_3D_S3
+#define MTPT_CAND_UNROLL_3D_S3 4
+#endif
 
 // Largest tile (cells in x, y and z) of the mass-transfer passes, the halo
-// cell rows it spans and the cell boundaries kept per halo row.
+// cell rows it spans and the cell boundaries kept per halo row.  Halo rows
+// (segments) are numbered with a fixed pitch per plane, seg_y (a power of two
+// in 3-d), and the tile's own rows with the same pitch, so that a row's plane
+// and the halo row of an own row follow from shifts and adds; col_p is the
+// power of two >= cols used to hand boundaries to threads.
 template <int D> struct TileLimits {
     static constexpr int max_x = D == 2 ? 24 : 12;
     static constexpr int max_y = D == 2 ? 24 : 6;
     static constexpr int max_z = D == 2 ? 1 : 6;
-    static constexpr int segs = (D == 3 ? max_z + 2 : 1) * (max_y + 2);
+    static constexpr int seg_y = max_y + 2;
+    static constexpr int segs = (D == 3 ? max_z + 2 : 1) * seg_y;
+    static constexpr int own_rows = (D == 3 ? max_z : 1) * seg_y;
     static constexpr int cols = max_x + 3;
+    static constexpr int col_p = D == 2 ? 32 : 16;
+    static_assert(D == 2 || (seg_y & (seg_y - 1)) == 0, "3-d halo rows need a power-of-two pitch");
+    static_assert(cols <= col_p, "column pitch too small");
 };
 inline int tile_max(int dim, int axis)
 {
