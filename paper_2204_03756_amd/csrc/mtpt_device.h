@@ -40,9 +40,10 @@ template <> struct Types<1> { using T = float;  using M = double; using A = doub
 template <> struct Types<2> { using T = float;  using M = float;  using A = float;  };
 
 // Particles a tile (cells plus halo) can stage in LDS: positions, and for the
-// transfer pass also row sums and masses.  Both passes take the capacity of
-// the transfer pass of the same species count, so that the row-sum pass
-// needs no more LDS than its tiles use; it stages positions only.
+// transfer pass also row sums and masses.  The row-sum pass (one
+// instantiation for every species count) takes the capacity of the
+// one-species transfer pass, so that it needs no more LDS than its tiles use
+// (it stages positions only); each pass has its own tile plan.
 template <int D, int PREC, int NS, bool TRANSFER> struct TileCap {
     using T = typename Types<PREC>::T;
     using M = typename Types<PREC>::M;
@@ -895,17 +896,20 @@ __device__ __forceinline__ void tile_body(const SimArgs& a, uint32_t blk)
 
     const int tid = threadIdx.x;
     const int nc0 = a.nc[0], nc1 = a.nc[1], nc2 = a.nc[2];
-    const uint32_t per_slab = a.tiles_x * a.tiles_y;
+    // this pass's tile plan
+    const int* const tl = TRANSFER ? a.ttile : a.tile;
+    const uint32_t tiles_x = TRANSFER ? a.ttiles_x : a.tiles_x;
+    const uint32_t per_slab = tiles_x * (TRANSFER ? a.ttiles_y : a.tiles_y);
     const int tzi = static_cast<int>(blk / per_slab);
     const uint32_t rem = blk - static_cast<uint32_t>(tzi) * per_slab;
-    const int tyi = static_cast<int>(rem / a.tiles_x);
-    const int txi = static_cast<int>(rem - static_cast<uint32_t>(tyi) * a.tiles_x);
-    const int x0 = txi * a.tile[0];
-    const int x1 = min(x0 + a.tile[0], nc0);
-    const int y0 = tyi * a.tile[1];
-    const int y1 = min(y0 + a.tile[1], nc1);
-    const int z0 = D == 3 ? tzi * a.tile[2] : 0;
-    const int z1 = D == 3 ? min(z0 + a.tile[2], nc2) : 1;
+    const int tyi = static_cast<int>(rem / tiles_x);
+    const int txi = static_cast<int>(rem - static_cast<uint32_t>(tyi) * tiles_x);
+    const int x0 = txi * tl[0];
+    const int x1 = min(x0 + tl[0], nc0);
+    const int y0 = tyi * tl[1];
+    const int y1 = min(y0 + tl[1], nc1);
+    const int z0 = D == 3 ? tzi * tl[2] : 0;
+    const int z1 = D == 3 ? min(z0 + tl[2], nc2) : 1;
     const int nrow = y1 - y0;                      // own rows per own plane
     const int nz = z1 - z0;                        // own planes (1 in 2-d)
     const int nown = nrow * nz;                    // own rows
@@ -989,9 +993,6 @@ __device__ __forceinline__ void tile_body(const SimArgs& a, uint32_t blk)
     __syncthreads();
 
     const bool use_lds = total <= static_cast<uint32_t>(CAP);
-    // the row-sum pass (one-species instantiation) staged this tile in LDS
-    // too, so it recorded the neighbour masks
-    const bool mask_ok = total <= static_cast<uint32_t>(TileCap<D, PREC, 1, false>::value);
     // cell boundaries of every halo row as LDS offsets (read by the particle
     // loop after the staging barrier)
     if (use_lds) {
@@ -1216,7 +1217,7 @@ __device__ __forceinline__ void tile_body(const SimArgs& a, uint32_t blk)
                 for (int d = 0; d < D; ++d)
                     jv[d] = static_cast<const T*>(a.jmp[d])[i];
             }
-            if (kEarly && mask_ok && act) {
+            if (kEarly && act) {
 #pragma unroll
                 for (int pzr = 0; pzr < planes; ++pzr)
                     mkp[pzr] = a.cmask[static_cast<size_t>(pzr) * static_cast<size_t>(a.n) + i];
@@ -1400,10 +1401,18 @@ __device__ __forceinline__ void tile_body(const SimArgs& a, uint32_t blk)
                     }
                 };
                 uint64_t* const pmask = a.cmask + static_cast<size_t>(pzr) * static_cast<size_t>(a.n);
-                if (TRANSFER && mask_ok && kmax <= 64u) {
+                // the recorded neighbours serve the wave when every lane has
+                // them (its row-sum tile was staged) and no lane has more
+                // than 63 candidates
+                uint64_t mk = 0ull;
+                bool use_mask = false;
+                if constexpr (TRANSFER) {
+                    mk = kEarly ? mkp[pzr] : (act ? pmask[i] : 0ull);
+                    use_mask = kmax <= 63u && __builtin_amdgcn_ballot_w64((mk & kMaskInvalid) != 0ull) == 0ull;
+                }
+                if (TRANSFER && use_mask) {
                     // neighbours recorded by the row-sum pass: bit k of the
                     // mask is candidate k (same rows, same order) within psi
-                    uint64_t mk = kEarly ? mkp[pzr] : (act ? pmask[i] : 0ull);
                     uint32_t cmax = static_cast<uint32_t>(__builtin_popcountll(mk));
                     cmax = wave_max_u32(cmax);
                     // a lane without a neighbour left visits its own slot:
@@ -1499,7 +1508,7 @@ __device__ __forceinline__ void tile_body(const SimArgs& a, uint32_t blk)
                     }
                 }
                 if (!TRANSFER && !EXPORT && act)
-                    pmask[i] = tot <= 64u ? ((static_cast<uint64_t>(mhi) << 32) | mlo) : 0ull;
+                    pmask[i] = tot <= 63u ? ((static_cast<uint64_t>(mhi) << 32) | mlo) : kMaskInvalid;
             }
         } else {
 #pragma unroll
@@ -1516,6 +1525,16 @@ __device__ __forceinline__ void tile_body(const SimArgs& a, uint32_t blk)
                         [&](uint32_t k) { return static_cast<const T*>(a.srow)[k]; },
                         [&](int c, uint32_t k) { return static_cast<const M*>(a.m_mid[c])[k]; }, b, e, 0u, xi,
                         xlo, xhi, i, acc, [&](uint32_t k) { if (act) record(k); });
+                }
+            }
+            // no recorded neighbours or windows for the transfer pass (whose
+            // tile may be staged)
+            if (!TRANSFER && !EXPORT && act) {
+#pragma unroll
+                for (int pzr = 0; pzr < planes; ++pzr) {
+                    a.cmask[static_cast<size_t>(pzr) * static_cast<size_t>(a.n) + i] = kMaskInvalid;
+                    if (kTrim && a.trim_rows)
+                        a.cwin[static_cast<size_t>(pzr) * static_cast<size_t>(a.n) + i] = 0ull;
                 }
             }
         }
@@ -1607,7 +1626,7 @@ __device__ __forceinline__ void finalize_body(const SimArgs& a, uint32_t nparts,
     if (mode == 0 && a.recompute_s) {
         unsigned long long p = 0;
 #pragma unroll 8
-        for (uint32_t b = threadIdx.x; b < nparts; b += NT)
+        for (uint32_t b = threadIdx.x; b < a.ntiles; b += NT)
             p += a.pair_part[b];
         pairs = block_sum<NT, unsigned long long>(p);
     }
@@ -1666,13 +1685,21 @@ __global__ __launch_bounds__(kBlock, D == 3 && PREC == 1 && !TN ? 7 : 1) void ro
 
 // the 2-d FP64 one-species transfer kernel is held to the registers of 5
 // workgroups per CU, which its LDS allows
+#ifndef MTPT_S3_MIN_BLOCKS
+#define MTPT_S3_MIN_BLOCKS 1
+#endif
+template <int D, int PREC, int NS>
+constexpr int transfer_min_blocks()
+{
+    return PREC == 0 && D == 2 && NS == 1 ? 5 : (D == 3 && PREC == 1 && NS == 3 ? MTPT_S3_MIN_BLOCKS : 1);
+}
 template <int D, int PREC, int NS, bool TN>
-__global__ __launch_bounds__(kBlock, PREC == 0 && D == 2 && NS == 1 ? 5 : 1) void transfer_k(SimArgs a)
+__global__ __launch_bounds__(kBlock, (transfer_min_blocks<D, PREC, NS>())) void transfer_k(SimArgs a)
 {
     tile_body<D, PREC, NS, true, TN>(a, xcd_block(blockIdx.x, gridDim.x));
 }
 template <int D, int PREC, int NS, bool TN>
-__global__ __launch_bounds__(kBlock, PREC == 0 && D == 2 && NS == 1 ? 5 : 1) void transfer_kb(Batch b)
+__global__ __launch_bounds__(kBlock, (transfer_min_blocks<D, PREC, NS>())) void transfer_kb(Batch b)
 {
     MTPT_BATCH_PROLOGUE;
     tile_body<D, PREC, NS, true, TN>(a, l);
@@ -1684,7 +1711,7 @@ __global__ __launch_bounds__(kBlock, PREC == 0 && D == 2 && NS == 1 ? 5 : 1) voi
 template <int D, bool TN>
 hipError_t launch_tiles(int ph, int prec, int ns, const SimArgs* a, const Batch* b, hipStream_t s)
 {
-    const uint32_t grid = a ? a->ntiles : b->total_blocks;
+    const uint32_t grid = a ? (ph == PH_ROWSUM ? a->ntiles : a->nttiles) : b->total_blocks;
     if (grid == 0 || (b && b->nsims == 0) || (a && a->n <= 0))
         return hipSuccess;
 #define MTPT_TILE_LAUNCH(KSIM, KBAT)                                                             \
@@ -1729,7 +1756,7 @@ __global__ __launch_bounds__(kBlock) void transfer_export_k(SimArgs a)
 template <int D, bool TN>
 hipError_t launch_tiles_export(int ph, int prec, int ns, const SimArgs& a, hipStream_t s)
 {
-    const uint32_t grid = a.ntiles;
+    const uint32_t grid = ph == PH_ROWSUM ? a.ntiles : a.nttiles;
     if (grid == 0 || a.n <= 0)
         return hipSuccess;
     if (ph == PH_ROWSUM) {

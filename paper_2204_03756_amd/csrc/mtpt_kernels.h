@@ -40,6 +40,9 @@ constexpr int kScanTile = kBlock * kScanItems;
 #define MTPT_TRIM_MIN_ROW 12.0
 #endif
 constexpr int kFinalBlock = 1024;    // threads of the finalize kernel
+// neighbour bits of a particle whose row-sum tile did not record them (a
+// recorded mask covers at most 63 candidates, so bit 63 is free)
+constexpr uint64_t kMaskInvalid = 1ull << 63;
 constexpr uint32_t kScanFold = 2048;  // scans of at most this many tiles skip the top pass
 // LDS staging budget (bytes) of a tile of the mass-transfer passes, per
 // dimension, precision and species count (3-d halos hold three planes of
@@ -58,9 +61,13 @@ constexpr uint32_t kScanFold = 2048;  // scans of at most this many tiles skip t
 #ifndef MTPT_LDS_BUDGET_3D_WIDE
 #define MTPT_LDS_BUDGET_3D_WIDE 46080
 #endif
-// 3-d three-species FP32-position passes
+// 3-d three-species FP32-position transfer pass: with 32 KiB and its candidate
+// loop unrolled by 2 (114 VGPRs) it holds four workgroups per CU (measured
+// 2.13 ms per launch on the 3.2e7-particle reacting workload, against 2.24 ms
+// with 45 KiB tiles at three workgroups per CU; 32 KiB unrolled by 4 at
+// three workgroups: 2.54 ms)
 #ifndef MTPT_LDS_BUDGET_3D_S3
-#define MTPT_LDS_BUDGET_3D_S3 46080
+#define MTPT_LDS_BUDGET_3D_S3 32768
 #endif
 template <int D, int PREC, int NS> struct LdsBudget {
     static constexpr int value =
@@ -92,7 +99,7 @@ template <int D, int PREC, int NS> struct LdsBudget {
 #endif
 // the 3-d three-species transfer pass (registers: its occupancy level)
 #ifndef MTPT_CAND_UNROLL_3D_S3
-#define MTPT_CAND_UNROLL_3D_S3 4
+#define MTPT_CAND_UNROLL_3D_S3 2
 #endif
 
 // Largest tile (cells in x, y and z) of the mass-transfer passes, the halo
@@ -143,9 +150,13 @@ struct SimArgs {
     int32_t nc[3];
     uint32_t ncells;
     // tiles of the mass-transfer passes: tx * ty * tz cells (tz = 1 in 2-d),
-    // numbered x fastest
+    // numbered x fastest; the row-sum pass (tile...) and the transfer pass
+    // (ttile...) each have their own plan (they differ when the transfer
+    // stages more species than the row-sum pass's positions)
     int32_t tile[3];
     uint32_t tiles_x, tiles_y, ntiles;
+    int32_t ttile[3];
+    uint32_t ttiles_x, ttiles_y, nttiles;
     // box and walk
     double lo[3], hi[3];
     float lof[3], hif[3];
@@ -186,7 +197,8 @@ struct SimArgs {
     uint32_t* perm;          // slot -> particle of the order before re-binning
     uint32_t* counts;        // per-cell histogram filled with global atomics
     uint32_t* tcounts;       // per-cell counts of particles that stayed in their tile
-    uint64_t* cmask;         // [plane][n] neighbour bits of the candidate rows (row-sum pass)
+    uint64_t* cmask;         // [plane][n] neighbour bits of the candidate rows (row-sum pass;
+                             // kMaskInvalid where the pass recorded none)
     uint64_t* cwin;          // [plane][n] x-windows of the trimmed rows (row-sum pass), or null
     uint32_t* starts;
     uint32_t* bsum;

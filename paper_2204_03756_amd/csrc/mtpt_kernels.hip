@@ -49,7 +49,7 @@ template <int D, int PREC>
 __global__ __launch_bounds__(kBlock) void place_fin_k(SimArgs a, SimArgs prev)
 {
     if (blockIdx.x == 0) {
-        finalize_body<kBlock>(prev, prev.ntiles, 0);
+        finalize_body<kBlock>(prev, prev.nttiles, 0);
         return;
     }
     place_body<D, typename Types<PREC>::T, typename Types<PREC>::M>(a, xcd_block(blockIdx.x - 1, gridDim.x - 1));
@@ -62,7 +62,7 @@ __global__ __launch_bounds__(kFinalBlock) void finalize_kb(Batch b)
 {
     MTPT_BATCH_PROLOGUE;
     (void)l;
-    finalize_body<kFinalBlock>(a, a.ntiles, 0);
+    finalize_body<kFinalBlock>(a, a.nttiles, 0);
 }
 
 #undef MTPT_BATCH_PROLOGUE
@@ -261,8 +261,8 @@ uint32_t phase_blocks(int ph, const SimArgs& a)
     case PH_SCAN_DOWN: return a.scan_blocks;
     case PH_SCAN_TOP:
     case PH_FINALIZE: return 1;
-    case PH_ROWSUM:
-    case PH_TRANSFER: return a.ntiles;
+    case PH_ROWSUM: return a.ntiles;
+    case PH_TRANSFER: return a.nttiles;
     default: return ceil_div(a.n, kBlock);
     }
 }
@@ -308,7 +308,7 @@ hipError_t launch_phase(int ph, int dim, int prec, const SimArgs& a, hipStream_t
                             : launch_tiles<2, false>(ph, prec, ns, &a, nullptr, s);
         return a.tensor ? launch_tiles<3, true>(ph, prec, ns, &a, nullptr, s)
                         : launch_tiles<3, false>(ph, prec, ns, &a, nullptr, s);
-    case PH_FINALIZE: finalize_k<<<1, kFinalBlock, 0, s>>>(a, a.ntiles, 0); break;
+    case PH_FINALIZE: finalize_k<<<1, kFinalBlock, 0, s>>>(a, a.nttiles, 0); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

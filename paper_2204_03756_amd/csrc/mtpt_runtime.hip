@@ -83,8 +83,10 @@ struct Plan {
     double inv_side[3] = {0, 0, 0};
     uint32_t ncells = 1;
     uint32_t scan_blocks = 1, part_blocks = 0;
-    int tile[3] = {1, 1, 1};
+    int tile[3] = {1, 1, 1};                  // row-sum pass
     uint32_t tiles_x = 1, tiles_y = 1, ntiles = 0;
+    int ttile[3] = {1, 1, 1};                 // transfer pass
+    uint32_t ttiles_x = 1, ttiles_y = 1, nttiles = 0;
     bool trim_rows = false;
     bool tensor = false;
     size_t tsz = 8, msz = 8;
@@ -277,50 +279,62 @@ Plan make_plan(const mtpt_params& p)
     // lane's candidate loop.
     {
         const double rho_c = static_cast<double>(q.n) / static_cast<double>(q.ncells);
-        const double cap = static_cast<double>(tile_capacity(q.dim, q.prec, q.ns)) / 1.25;
 #ifndef MTPT_TILE_OWN
 #define MTPT_TILE_OWN 640.0
 #endif
 #ifndef MTPT_TILE_LANES
 #define MTPT_TILE_LANES 64.0
 #endif
-        int tx = 1, ty = 1, tz = 1;
-        if (q.dim == 2) {
-            const double cells_own = std::max(1.0, MTPT_TILE_OWN / std::max(rho_c, 1e-9));
-            const int t = static_cast<int>(std::lround(std::sqrt(cells_own)));
-            tx = std::max(1, std::min(t, std::min(q.nc[0], tile_max(2, 0))));
-            ty = std::max(1, std::min(t, std::min(q.nc[1], tile_max(2, 1))));
-            while ((tx + 2.0) * (ty + 2.0) * rho_c > cap && (tx > 1 || ty > 1)) {
-                if (tx >= ty)
-                    --tx;
-                else
-                    --ty;
-            }
-        } else {
-            double best = 0.0;
-            for (int z = 1; z <= std::min(q.nc[2], tile_max(3, 2)); ++z)
-                for (int y = 1; y <= std::min(q.nc[1], tile_max(3, 1)); ++y)
-                    for (int x = 1; x <= std::min(q.nc[0], tile_max(3, 0)); ++x) {
-                        const double halo = (x + 2.0) * (y + 2.0) * (z + 2.0) * rho_c;
-                        if (halo > cap && !(x == 1 && y == 1 && z == 1))
-                            continue;
-                        const double own = std::max(1e-9, x * y * static_cast<double>(z) * rho_c);
-                        const double passes = std::ceil((own + 2.0 * std::sqrt(own)) / MTPT_TILE_LANES);
-                        const double cost = (passes * MTPT_TILE_LANES + 0.02 * halo + 25.0) / own;
-                        if (best == 0.0 || cost < best) {
-                            best = cost;
-                            tx = x;
-                            ty = y;
-                            tz = z;
+        // the tile shape for a staging capacity of capn particles
+        auto choose = [&](int capn, int* t) {
+            const double cap = static_cast<double>(capn) / 1.25;
+            int tx = 1, ty = 1, tz = 1;
+            if (q.dim == 2) {
+                const double cells_own = std::max(1.0, MTPT_TILE_OWN / std::max(rho_c, 1e-9));
+                const int tt = static_cast<int>(std::lround(std::sqrt(cells_own)));
+                tx = std::max(1, std::min(tt, std::min(q.nc[0], tile_max(2, 0))));
+                ty = std::max(1, std::min(tt, std::min(q.nc[1], tile_max(2, 1))));
+                while ((tx + 2.0) * (ty + 2.0) * rho_c > cap && (tx > 1 || ty > 1)) {
+                    if (tx >= ty)
+                        --tx;
+                    else
+                        --ty;
+                }
+            } else {
+                double best = 0.0;
+                for (int z = 1; z <= std::min(q.nc[2], tile_max(3, 2)); ++z)
+                    for (int y = 1; y <= std::min(q.nc[1], tile_max(3, 1)); ++y)
+                        for (int x = 1; x <= std::min(q.nc[0], tile_max(3, 0)); ++x) {
+                            const double halo = (x + 2.0) * (y + 2.0) * (z + 2.0) * rho_c;
+                            if (halo > cap && !(x == 1 && y == 1 && z == 1))
+                                continue;
+                            const double own = std::max(1e-9, x * y * static_cast<double>(z) * rho_c);
+                            const double passes = std::ceil((own + 2.0 * std::sqrt(own)) / MTPT_TILE_LANES);
+                            const double cost = (passes * MTPT_TILE_LANES + 0.02 * halo + 25.0) / own;
+                            if (best == 0.0 || cost < best) {
+                                best = cost;
+                                tx = x;
+                                ty = y;
+                                tz = z;
+                            }
                         }
-                    }
-        }
-        q.tile[0] = tx;
-        q.tile[1] = ty;
-        q.tile[2] = tz;
-        q.tiles_x = static_cast<uint32_t>((q.nc[0] + tx - 1) / tx);
-        q.tiles_y = static_cast<uint32_t>((q.nc[1] + ty - 1) / ty);
-        q.ntiles = q.tiles_x * q.tiles_y * static_cast<uint32_t>(q.dim == 3 ? (q.nc[2] + tz - 1) / tz : 1);
+            }
+            t[0] = tx;
+            t[1] = ty;
+            t[2] = tz;
+        };
+        // the row-sum pass stages positions only (its capacity is that of the
+        // one-species transfer pass); the transfer pass stages row sums and
+        // every species too
+        choose(tile_capacity(q.dim, q.prec, 1), q.tile);
+        choose(tile_capacity(q.dim, q.prec, q.ns), q.ttile);
+        auto count = [&](const int* t, uint32_t* txs, uint32_t* tys) {
+            *txs = static_cast<uint32_t>((q.nc[0] + t[0] - 1) / t[0]);
+            *tys = static_cast<uint32_t>((q.nc[1] + t[1] - 1) / t[1]);
+            return *txs * *tys * static_cast<uint32_t>(q.dim == 3 ? (q.nc[2] + t[2] - 1) / t[2] : 1);
+        };
+        q.ntiles = count(q.tile, &q.tiles_x, &q.tiles_y);
+        q.nttiles = count(q.ttile, &q.ttiles_x, &q.ttiles_y);
         // rows of three cells long enough that trimming them to the x-window
         // saves more candidates than its two binary searches cost
         q.trim_rows = !q.tensor && 3.0 * rho_c >= MTPT_TRIM_MIN_ROW;
@@ -355,7 +369,7 @@ Plan make_plan(const mtpt_params& p)
     q.off_tcounts = take(padded * 4);
     q.off_starts = take(padded * 4);
     q.off_bsum = take(static_cast<size_t>(q.scan_blocks) * 4);
-    q.off_part = take(static_cast<size_t>(std::max<uint32_t>(std::max(q.part_blocks, q.ntiles), 1)) * 3 * 8);
+    q.off_part = take(static_cast<size_t>(std::max<uint32_t>(std::max(q.part_blocks, q.nttiles), 1)) * 3 * 8);
     q.off_pair = take(static_cast<size_t>(std::max<uint32_t>(q.ntiles, 1)) * 4);
     q.off_stats = take(sizeof(DevStats));
     q.bytes = off;
@@ -465,6 +479,11 @@ SimArgs base_args(const mtpt_sim* s)
     a.tiles_x = q.tiles_x;
     a.tiles_y = q.tiles_y;
     a.ntiles = q.ntiles;
+    for (int k = 0; k < 3; ++k)
+        a.ttile[k] = q.ttile[k];
+    a.ttiles_x = q.ttiles_x;
+    a.ttiles_y = q.ttiles_y;
+    a.nttiles = q.nttiles;
     a.trim_rows = q.trim_rows ? 1 : 0;
     a.sdev = std::sqrt(2.0 * p.d_rw * p.dt);
     for (int k = 0; k < 3; ++k)
