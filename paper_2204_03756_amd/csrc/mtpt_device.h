@@ -637,10 +637,13 @@ __device__ __forceinline__ void place_body(const SimArgs& a, uint32_t blk)
             xv[d] = static_cast<const T*>(a.xt[d])[src];
         kp = a.pid_src[src];
         // the masses are gathered with the keys, not after the ranking
+        // (unless the row-sum pass moves them)
+        if (!a.src_slot) {
 #pragma unroll
-        for (int s = 0; s < 3; ++s)
-            if (s < a.ns)
-                mv[s] = static_cast<const M*>(a.m_src[s])[src];
+            for (int s = 0; s < 3; ++s)
+                if (s < a.ns)
+                    mv[s] = static_cast<const M*>(a.m_src[s])[src];
+        }
         const uint32_t c = cell_index<D, T>(a, xv);
         b = a.starts[c];
         e = a.starts[c + 1];
@@ -680,10 +683,14 @@ __device__ __forceinline__ void place_body(const SimArgs& a, uint32_t blk)
 #pragma unroll
     for (int d = 0; d < D; ++d)
         static_cast<T*>(a.x[d])[dst] = xv[d];
+    if (a.src_slot) {
+        a.src_slot[dst] = src;
+    } else {
 #pragma unroll
-    for (int s = 0; s < 3; ++s)
-        if (s < a.ns)
-            static_cast<M*>(a.m_mid[s])[dst] = mv[s];
+        for (int s = 0; s < 3; ++s)
+            if (s < a.ns)
+                static_cast<M*>(a.m_mid[s])[dst] = mv[s];
+    }
     a.pid_dst[dst] = kp;
     if (a.fuse_bin) {
 #pragma unroll
@@ -1550,6 +1557,16 @@ __device__ __forceinline__ void tile_body(const SimArgs& a, uint32_t blk)
         if constexpr (!TRANSFER) {
             static_cast<T*>(a.srow)[i] = acc.s;
             pairs += acc.cnt - 1u;
+            if (a.src_slot) {
+                // the masses of the sorted slot, from the order before
+                // re-binning (the place pass recorded the source slot): a
+                // gather whose latency the arithmetic of the other waves hides
+                const uint32_t src = a.src_slot[i];
+#pragma unroll
+                for (int c = 0; c < 3; ++c)
+                    if (c < a.ns)
+                        static_cast<M*>(a.m_mid[c])[i] = static_cast<const M*>(a.m_src[c])[src];
+            }
         } else {
             // the next step's walk and binning first: the slot's atomic (for
             // a particle that leaves the tile) is in flight during the mass

@@ -195,6 +195,10 @@ struct SimArgs {
     uint32_t* cell;
     uint32_t* rank;
     uint32_t* perm;          // slot -> particle of the order before re-binning
+    uint32_t* src_slot;      // null, or: the place pass records each sorted slot's
+                             // particle of the order before re-binning here (the
+                             // cell buffer, free by then) and leaves the masses to
+                             // the row-sum pass, which gathers them from m_src
     uint32_t* counts;        // per-cell histogram filled with global atomics
     uint32_t* tcounts;       // per-cell counts of particles that stayed in their tile
     uint64_t* cmask;         // [plane][n] neighbour bits of the candidate rows (row-sum pass;
