@@ -1361,8 +1361,18 @@ __device__ __forceinline__ void tile_body(const SimArgs& a, uint32_t blk)
                     return *reinterpret_cast<const std::remove_cv_t<std::remove_reference_t<decltype(*base)>>*>(
                         reinterpret_cast<const char*>(base) + off);
                 };
-                uint32_t kmax = tot;
-                kmax = wave_max_u32(kmax);
+                // the recorded neighbours serve the wave when every lane has
+                // them (its row-sum tile was staged) and no lane has more
+                // than 63 candidates (ballots: the wave-wide maximum is needed
+                // only by the candidate loop)
+                uint64_t mk = 0ull;
+                bool use_mask = false, fits32 = false;
+                if constexpr (TRANSFER) {
+                    mk = kEarly ? mkp[pzr] : (act ? a.cmask[static_cast<size_t>(pzr) * static_cast<size_t>(a.n) + i] : 0ull);
+                    use_mask = __builtin_amdgcn_ballot_w64(tot > 63u || (mk & kMaskInvalid) != 0ull) == 0ull;
+                    fits32 = __builtin_amdgcn_ballot_w64(tot > 32u) == 0ull;
+                }
+                const uint32_t kmax = use_mask ? 0u : wave_max_u32(tot);
                 constexpr int kUnroll = D == 3 ? (TRANSFER && NS == 3 ? MTPT_CAND_UNROLL_3D_S3 : MTPT_CAND_UNROLL_3D)
                                                : (PREC == 0 ? MTPT_CAND_UNROLL_2D_F64 : MTPT_CAND_UNROLL_2D);
                 // one candidate at LDS byte offset off (of the T arrays), pair
@@ -1408,15 +1418,6 @@ __device__ __forceinline__ void tile_body(const SimArgs& a, uint32_t blk)
                     }
                 };
                 uint64_t* const pmask = a.cmask + static_cast<size_t>(pzr) * static_cast<size_t>(a.n);
-                // the recorded neighbours serve the wave when every lane has
-                // them (its row-sum tile was staged) and no lane has more
-                // than 63 candidates
-                uint64_t mk = 0ull;
-                bool use_mask = false;
-                if constexpr (TRANSFER) {
-                    mk = kEarly ? mkp[pzr] : (act ? pmask[i] : 0ull);
-                    use_mask = kmax <= 63u && __builtin_amdgcn_ballot_w64((mk & kMaskInvalid) != 0ull) == 0ull;
-                }
                 if (TRANSFER && use_mask) {
                     // neighbours recorded by the row-sum pass: bit k of the
                     // mask is candidate k (same rows, same order) within psi
@@ -1433,7 +1434,7 @@ __device__ __forceinline__ void tile_body(const SimArgs& a, uint32_t blk)
                             xj[d] = ld(lpos[d], off);
                         visit(off, PREC == 2 ? valid : true, Metric<D, T, TN>::r2(a, xi, xj));
                     };
-                    if (kmax <= 32u) {
+                    if (fits32) {
                         // every lane's candidates fit the low word
                         uint32_t m32 = static_cast<uint32_t>(mk);
 #pragma unroll kUnroll
