@@ -98,12 +98,34 @@ def _dense3d(n, density, prec):
     return W.Workload(f"dense3d-rho{density}", p, x, m, 2, {})
 
 
+def _ramp3s(prec):
+    """Three species, A+B->C, particle density rising 10-fold along x (0.3 to 3
+    times the mean of 1): the row-sum and transfer passes tile the grid
+    differently (positions only, against positions, row sums and three
+    species), so where the density crosses their LDS capacities some
+    particles' row-sum tiles overflow (no recorded neighbours) while their
+    transfer tiles are staged, and the reverse."""
+    lx, ly, lz = 60.0, 30.0, 30.0
+    n = int(lx * ly * lz * 1.65)
+    p = W.Params(dim=3, n=n, lo=[0.0, 0.0, 0.0], hi=[lx, ly, lz], d_rw=0.3, d_mt=0.7, dt=0.05,
+                 beta=0.5, psi=0.0, k_react=1.0, n_species=3, seed=0x4D5450541D, precision=prec)
+    rng = np.random.Generator(np.random.Philox(20221205))
+    # x from the density 0.3 + 2.7 u (u = x / lx) by its inverse distribution
+    a, b = 0.3, 2.7
+    r = rng.random(n) * (a + b / 2.0)
+    u = (-a + np.sqrt(a * a + 2.0 * b * r)) / b
+    x = np.stack([np.clip(u * lx, 0.0, lx), rng.random(n) * ly, rng.random(n) * lz], axis=1)
+    ma = (x[:, 1] < ly / 2).astype(np.float64)
+    return W.Workload("ramp3s", p, x, np.stack([ma, 1.0 - ma, np.zeros(n)]), 3, {})
+
+
 HOT_CASES = [
     ("rw2d", W.FP64), ("rw2d", W.FP32W_FP64ACC),
     ("rw3d", W.FP64), ("rw3d", W.FP32W_FP64ACC), ("rw3d", W.FP32_KAHAN),
     ("react3d", W.FP64), ("react3d", W.FP32W_FP64ACC),
     ("dense3d4", W.FP32W_FP64ACC), ("dense3d4", W.FP64), ("dense3d20", W.FP32W_FP64ACC),
     ("tens3d", W.FP32W_FP64ACC), ("plain2d", W.FP64),
+    ("ramp3s", W.FP32W_FP64ACC), ("ramp3s", W.FP64),
 ]
 
 
@@ -127,13 +149,15 @@ def test_hot_path_neighbor_sets(mt, oracle, case, prec):
         w = _dense3d(30_000, 4.0, prec)      # rows of ~80: waves past 64 candidates
     elif case == "dense3d20":
         w = _dense3d(30_000, 20.0, prec)     # halos beyond the LDS: global path
+    elif case == "ramp3s":
+        w = _ramp3s(prec)
     elif case == "tens3d":
         w0 = W.rw3d(n=20_000 + 7, steps=3, precision=prec, n_src=20)
         w = W.Workload("tens3d", W.replace(w0.params, disp=W.rotated_tensor([2.5, 0.8, 0.5], [0.4, -0.3, 0.2])),
                        w0.x0, w0.m0, 3, {})
     else:
         w = W.plain2d(n=20_000, steps=3, precision=prec)
-    steps = w.steps if case.startswith("dense") else 3
+    steps = w.steps if case.startswith("dense") or case == "ramp3s" else 3
     say(f"  hot-path neighbours {case} {PREC_NAMES[prec]} n={w.params.n}")
     x, rs, tr = _hot_sets(mt, w, steps)
     ref = oracle_run(oracle, w, steps)
