@@ -134,7 +134,8 @@ struct DevStats {
     int pad0;
     double totals[3];                // mass totals after the last step
     long long steps;                 // steps completed on the device
-    double pad[3];
+    double initial[3];               // totals after the set-up binning (copied on the
+                                     // device, read when the statistics are asked for)
 };
 
 // Everything one launch of one phase needs about one simulation.  Pointers
@@ -289,6 +290,8 @@ hipError_t launch_nb_count(int dim, int prec, const SimArgs& a, const uint32_t* 
                            uint32_t* rowcnt, hipStream_t s);
 hipError_t launch_nb_fill(int dim, int prec, const SimArgs& a, const uint32_t* pid_cur,
                           const int64_t* row_ptr, int64_t* col, hipStream_t s);
+// out[i] = i for i < n (the pids of the input order)
+hipError_t launch_iota(uint32_t* out, int64_t n, hipStream_t s);
 hipError_t launch_scan_u32_to_i64(const uint32_t* in, int64_t* out, int64_t len, uint32_t* tmp,
                                   uint32_t* bsum, hipStream_t s);
 

@@ -82,6 +82,13 @@ __global__ __launch_bounds__(kBlock) void unpermute_mass_k(int64_t n, int ns, co
     }
 }
 
+__global__ __launch_bounds__(kBlock) void iota_k(uint32_t* out, int64_t n)
+{
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+    if (i < n)
+        out[i] = static_cast<uint32_t>(i);
+}
+
 template <int D, typename T>
 __global__ __launch_bounds__(kBlock) void unpermute_pos_k(int64_t n, const T* x0, const T* x1, const T* x2,
                                                           const uint32_t* pid, double* out)
@@ -396,6 +403,13 @@ hipError_t launch_unpermute_pos(int dim, int prec, const SimArgs& a, const uint3
         if (dim == 2) unpermute_pos_k<2, float><<<grid, kBlock, 0, s>>>(a.n, x[0], x[1], x[2], pid_cur, out);
         else unpermute_pos_k<3, float><<<grid, kBlock, 0, s>>>(a.n, x[0], x[1], x[2], pid_cur, out);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_iota(uint32_t* out, int64_t n, hipStream_t s)
+{
+    if (n > 0)
+        iota_k<<<ceil_div(n, kBlock), kBlock, 0, s>>>(out, n);
     return hipGetLastError();
 }
 

@@ -414,6 +414,8 @@ struct mtpt_sim {
     bool fin_pending = false;
     SimArgs fin_args{};
     double mass_initial[3]{};
+    bool mass_initial_known = false;   // else in DevStats.initial
+    hipEvent_t done_ev = nullptr;      // serving: recorded behind the sim's last step
     // profiling
     bool profiling = false;
     std::vector<PhaseEv> evs;
@@ -721,16 +723,31 @@ void release(mtpt_sim* s)
     s->evs.clear();
     s->alloc.put(s->base);
     s->base = nullptr;
+    if (s->done_ev)
+        (void)hipEventDestroy(s->done_ev);
     if (s->own_stream && s->stream)
         (void)hipStreamDestroy(s->stream);
     delete s;
 }
 
+// Pinned host staging of one admission (serving pool): reused once the
+// event recorded behind its copies has fired.
+struct PinnedStage {
+    void* host = nullptr;
+    size_t cap = 0;
+    hipEvent_t ev = nullptr;
+    bool armed = false;
+};
+
 // Upload inputs and bin them (the state at step 0).  Positions (and Kahan
-// masses) are converted on the host into pageable staging and copied with
-// blocking copies; the binning and the initial totals are enqueued on the
-// sim's stream, and create waits for them (the initial totals are read back).
-int create_into(mtpt_sim* s, const double* pos, const double* mass)
+// masses) are converted on the host into staging; the pids are filled on the
+// device; the binning, the initial totals and their copy into DevStats.initial
+// are enqueued on the sim's stream.  Without st (mtpt_create) the staging is
+// pageable, the copies block, and create waits for the binning and reads the
+// initial totals.  With st (pool admission) the staging is pinned, the copies
+// are asynchronous, the event st->ev is recorded behind them, and nothing
+// waits: the initial totals are read when the statistics are first asked for.
+int create_into(mtpt_sim* s, const double* pos, const double* mass, PinnedStage* st = nullptr)
 {
     const Plan& q = s->q;
     const size_t n = static_cast<size_t>(q.n);
@@ -738,34 +755,56 @@ int create_into(mtpt_sim* s, const double* pos, const double* mass)
     HIP_TRY(hipMemsetAsync(s->counts, 0, static_cast<size_t>(q.scan_blocks) * kScanTile * 4, s->stream));
     HIP_TRY(hipMemsetAsync(s->tcounts, 0, static_cast<size_t>(q.scan_blocks) * kScanTile * 4, s->stream));
     if (n > 0) {
-        std::vector<unsigned char> stage(std::max(n * q.tsz, n * q.msz));
+        std::vector<unsigned char> pageable;
+        unsigned char* stage = nullptr;
+        if (st) {
+            stage = static_cast<unsigned char*>(st->host);
+        } else {
+            pageable.resize(std::max(n * q.tsz, n * q.msz));
+            stage = pageable.data();
+        }
+        // the pinned staging holds every array at once: [dim][n] positions, then
+        // [ns][n] masses; the pageable one one array at a time
+        size_t off = 0;
+        auto upload = [&](void* dst, size_t bytes, const unsigned char* src) -> hipError_t {
+            return st ? hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s->stream)
+                      : hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice);
+        };
         for (int k = 0; k < q.dim; ++k) {
             // coordinate k, rounded once to the position type
+            unsigned char* h = stage + off;
             if (q.tsz == 8) {
-                double* d = reinterpret_cast<double*>(stage.data());
+                double* d = reinterpret_cast<double*>(h);
                 for (size_t i = 0; i < n; ++i)
                     d[i] = pos[i * q.dim + k];
             } else {
-                float* f = reinterpret_cast<float*>(stage.data());
+                float* f = reinterpret_cast<float*>(h);
                 for (size_t i = 0; i < n; ++i)
                     f[i] = static_cast<float>(pos[i * q.dim + k]);
             }
-            HIP_TRY(hipMemcpy(s->X[k], stage.data(), n * q.tsz, hipMemcpyHostToDevice));
+            HIP_TRY(upload(s->X[k], n * q.tsz, h));
+            if (st)
+                off += n * q.tsz;
         }
         for (int c = 0; c < q.ns; ++c) {
+            unsigned char* h = stage + off;
             if (q.msz == 8) {
-                HIP_TRY(hipMemcpy(s->M[1][c], mass + c * n, n * 8, hipMemcpyHostToDevice));
+                if (st) {
+                    std::memcpy(h, mass + c * n, n * 8);
+                    HIP_TRY(upload(s->M[1][c], n * 8, h));
+                } else {
+                    HIP_TRY(hipMemcpy(s->M[1][c], mass + c * n, n * 8, hipMemcpyHostToDevice));
+                }
             } else {
-                float* f = reinterpret_cast<float*>(stage.data());
+                float* f = reinterpret_cast<float*>(h);
                 for (size_t i = 0; i < n; ++i)
                     f[i] = static_cast<float>(mass[c * n + i]);
-                HIP_TRY(hipMemcpy(s->M[1][c], stage.data(), n * 4, hipMemcpyHostToDevice));
+                HIP_TRY(upload(s->M[1][c], n * 4, h));
             }
+            if (st)
+                off += n * q.msz;
         }
-        std::vector<uint32_t> ident(n);
-        for (size_t i = 0; i < n; ++i)
-            ident[i] = static_cast<uint32_t>(i);
-        HIP_TRY(hipMemcpy(s->P[1], ident.data(), n * 4, hipMemcpyHostToDevice));
+        HIP_TRY(launch_iota(s->P[1], q.n, s->stream));
         // initial binning: positions in pid order, no jump; pids P1 -> P0,
         // masses M1 -> M0
         SimArgs a = base_args(s);
@@ -782,6 +821,14 @@ int create_into(mtpt_sim* s, const double* pos, const double* mass)
         if (rc)
             return rc;
         HIP_TRY(launch_totals(q.prec, a, s->M[0], s->stream));
+        HIP_TRY(hipMemcpyAsync(&s->st->initial[0], &s->st->totals[0], sizeof(double) * 3,
+                               hipMemcpyDeviceToDevice, s->stream));
+    }
+    if (st) {
+        HIP_TRY(hipEventRecord(st->ev, s->stream));
+        st->armed = true;
+        s->mass_initial_known = false;
+        return MTPT_OK;
     }
     const int rc = sync(s);
     if (rc)
@@ -792,6 +839,7 @@ int create_into(mtpt_sim* s, const double* pos, const double* mass)
     HIP_TRY(hipMemcpy(&h, s->st, sizeof h, hipMemcpyDeviceToHost));
     for (int c = 0; c < 3; ++c)
         s->mass_initial[c] = c < q.ns ? h.totals[c] : 0.0;
+    s->mass_initial_known = true;
     return MTPT_OK;
 }
 
@@ -813,7 +861,7 @@ int check_inputs(const mtpt_params& p, const double* pos, const double* mass)
 }
 
 int new_sim(const mtpt_params* params, const double* pos, const double* mass, void* hip_stream,
-            const mtpt_allocator* alloc, mtpt_sim** out)
+            const mtpt_allocator* alloc, mtpt_sim** out, PinnedStage* st = nullptr)
 {
     int rc = validate(params);
     if (rc)
@@ -856,7 +904,7 @@ int new_sim(const mtpt_params* params, const double* pos, const double* mass, vo
         return fail(MTPT_E_NOMEM, "device allocation of %zu bytes failed", s->q.bytes);
     }
     carve(s);
-    rc = create_into(s, pos, mass);
+    rc = create_into(s, pos, mass, st);
     if (rc) {
         std::string msg = g_err;
         (void)hipStreamSynchronize(s->stream);
@@ -978,6 +1026,11 @@ int mtpt_stats(mtpt_sim* s, mtpt_stats_t* out)
         return rc;
     DevStats h{};
     HIP_TRY(hipMemcpy(&h, s->st, sizeof h, hipMemcpyDeviceToHost));
+    if (!s->mass_initial_known) {
+        for (int c = 0; c < 3; ++c)
+            s->mass_initial[c] = c < s->q.ns ? h.initial[c] : 0.0;
+        s->mass_initial_known = true;
+    }
     std::memset(out, 0, sizeof *out);
     out->steps_done = s->steps_done;
     out->pairs_last = static_cast<int64_t>(h.pairs_last);
@@ -1323,6 +1376,8 @@ struct mtpt_pool {
     int64_t next_ticket = 1;
     RingSlot ring[4];
     int64_t ticks = 0;
+    std::deque<PinnedStage> stages;      // admission staging (at most kStages)
+    hipStream_t xstream = nullptr;       // exports of finished sims
 };
 
 namespace {
@@ -1350,6 +1405,66 @@ int ring_reserve(mtpt_pool* p, RingSlot& r, size_t bytes)
         return fail(MTPT_E_NOMEM, "pool argument buffer allocation failed");
     r.cap = cap;
     return MTPT_OK;
+}
+
+// A pinned staging buffer of at least bytes whose previous copies have
+// finished: a free one (grown if needed), else a new one while there are
+// fewer than kStages, else the oldest once its copies are done.
+constexpr size_t kStages = 4;
+int stage_acquire(mtpt_pool* p, size_t bytes, PinnedStage** out)
+{
+    PinnedStage* pick = nullptr;
+    for (auto& g : p->stages) {
+        if (g.armed) {
+            const hipError_t e = hipEventQuery(g.ev);
+            if (e == hipErrorNotReady) {
+                (void)hipGetLastError();
+                continue;
+            }
+            if (e != hipSuccess)
+                return fail(MTPT_E_DEVICE, "staging event: %s", hipGetErrorString(e));
+            g.armed = false;
+        }
+        if (!pick || (pick->cap < bytes && g.cap >= bytes))
+            pick = &g;
+    }
+    if (!pick && p->stages.size() < kStages) {
+        p->stages.emplace_back();
+        pick = &p->stages.back();
+        HIP_TRY(hipEventCreateWithFlags(&pick->ev, hipEventDisableTiming));
+    }
+    if (!pick) {
+        pick = &p->stages.front();
+        HIP_TRY(hipEventSynchronize(pick->ev));
+        pick->armed = false;
+    }
+    if (pick->cap < bytes) {
+        if (pick->host)
+            (void)hipHostFree(pick->host);
+        pick->host = nullptr;
+        pick->cap = 0;
+        const size_t cap = align_up(std::max<size_t>(bytes, 1 << 20), 1 << 16);
+        HIP_TRY(hipHostMalloc(&pick->host, cap, hipHostMallocDefault));
+        pick->cap = cap;
+    }
+    *out = pick;
+    return MTPT_OK;
+}
+
+// Run fn for sim s on the pool's export stream when s has finished (the
+// stream first waits for the event behind s's last step, so that fn does not
+// wait for the ticks of the other sims), else on the pool stream.
+template <typename F>
+int on_export_stream(mtpt_pool* p, mtpt_sim* s, F fn)
+{
+    if (!(s->done_ev && s->steps_done >= s->steps_target && p->xstream))
+        return fn();
+    HIP_TRY(hipStreamWaitEvent(p->xstream, s->done_ev, 0));
+    hipStream_t keep = s->stream;
+    s->stream = p->xstream;
+    const int rc = fn();
+    s->stream = keep;
+    return rc;
 }
 
 struct GroupKey {
@@ -1404,6 +1519,12 @@ int mtpt_pool_create(size_t hbm_budget, int32_t max_slots, void* hip_stream, con
         }
         p->own_stream = true;
     }
+    if (hipStreamCreateWithFlags(&p->xstream, hipStreamNonBlocking) != hipSuccess) {
+        if (p->own_stream)
+            (void)hipStreamDestroy(p->stream);
+        delete p;
+        return fail(MTPT_E_DEVICE, "hipStreamCreateWithFlags failed");
+    }
     *out = p;
     return MTPT_OK;
 }
@@ -1425,8 +1546,15 @@ int mtpt_pool_admit(mtpt_pool* p, const mtpt_params* params, const double* pos, 
         return fail(MTPT_E_NOMEM, "no free slot (%d active)", static_cast<int>(p->sims.size()));
     if (p->held + need > p->budget)
         return fail(MTPT_E_NOMEM, "budget: %zu held + %zu needed > %zu", p->held, need, p->budget);
+    // inputs staged through pinned memory and uploaded asynchronously: the
+    // admission does not wait for the ticks in flight
+    PinnedStage* stage = nullptr;
+    rc = stage_acquire(p, static_cast<size_t>(q.n) * (static_cast<size_t>(q.dim) * q.tsz + static_cast<size_t>(q.ns) * q.msz),
+                       &stage);
+    if (rc)
+        return rc;
     mtpt_sim* s = nullptr;
-    rc = new_sim(params, pos, mass, p->stream, p->alloc.custom ? &p->alloc.a : nullptr, &s);
+    rc = new_sim(params, pos, mass, p->stream, p->alloc.custom ? &p->alloc.a : nullptr, &s, stage);
     if (rc)
         return rc;
     s->steps_target = n_steps;
@@ -1523,8 +1651,13 @@ int mtpt_pool_tick(mtpt_pool* p, int32_t* n_completed)
                     s->s_valid = true;
                 else
                     s->bin_ready = true;
-                if (s->steps_done == s->steps_target)
+                if (s->steps_done == s->steps_target) {
                     ++completed;
+                    // done() and the exports wait for this event only
+                    if (!s->done_ev)
+                        HIP_TRY(hipEventCreateWithFlags(&s->done_ev, hipEventDisableTiming));
+                    HIP_TRY(hipEventRecord(s->done_ev, p->stream));
+                }
             }
             ++gi;
         }
@@ -1547,7 +1680,19 @@ int mtpt_pool_done(mtpt_pool* p, int64_t ticket, int32_t* done)
     mtpt_sim* s = it->second;
     *done = 0;
     if (s->steps_done >= s->steps_target) {
-        HIP_TRY(hipStreamSynchronize(p->stream));
+        if (!s->done_ev) {
+            HIP_TRY(hipStreamSynchronize(p->stream));
+            *done = 1;
+            return MTPT_OK;
+        }
+        // a query, not a wait: the ticks of the other sims keep running
+        const hipError_t e = hipEventQuery(s->done_ev);
+        if (e == hipErrorNotReady) {
+            (void)hipGetLastError();
+            return MTPT_OK;
+        }
+        if (e != hipSuccess)
+            return fail(MTPT_E_DEVICE, "mtpt_pool_done: %s", hipGetErrorString(e));
         *done = 1;
     }
     return MTPT_OK;
@@ -1560,7 +1705,8 @@ int mtpt_pool_stats(mtpt_pool* p, int64_t ticket, mtpt_stats_t* out)
     auto it = p->sims.find(ticket);
     if (it == p->sims.end())
         return fail(MTPT_E_ARG, "unknown ticket %lld", (long long)ticket);
-    return mtpt_stats(it->second, out);
+    mtpt_sim* s = it->second;
+    return on_export_stream(p, s, [&] { return mtpt_stats(s, out); });
 }
 
 int mtpt_pool_result(mtpt_pool* p, int64_t ticket, double* mass_out)
@@ -1574,10 +1720,11 @@ int mtpt_pool_result(mtpt_pool* p, int64_t ticket, double* mass_out)
     if (s->steps_done < s->steps_target)
         return fail(MTPT_E_STATE, "ticket %lld has %lld of %lld steps", (long long)ticket,
                     (long long)s->steps_done, (long long)s->steps_target);
-    const int rc = mtpt_masses(s, mass_out);
+    const int rc = on_export_stream(p, s, [&] { return mtpt_masses(s, mass_out); });
     if (rc && rc != MTPT_E_NONFINITE)
         return rc;
-    (void)hipStreamSynchronize(p->stream);
+    if (!s->done_ev)
+        (void)hipStreamSynchronize(p->stream);
     release(s);
     p->held -= p->bytes_of[ticket];
     p->bytes_of.erase(ticket);
@@ -1603,9 +1750,20 @@ int mtpt_pool_destroy(mtpt_pool* p)
     if (!p)
         return MTPT_OK;
     (void)hipStreamSynchronize(p->stream);
+    if (p->xstream)
+        (void)hipStreamSynchronize(p->xstream);
     for (auto& kv : p->sims)
         release(kv.second);
     p->sims.clear();
+    for (auto& g : p->stages) {
+        if (g.host)
+            (void)hipHostFree(g.host);
+        if (g.ev)
+            (void)hipEventDestroy(g.ev);
+    }
+    p->stages.clear();
+    if (p->xstream)
+        (void)hipStreamDestroy(p->xstream);
     for (auto& r : p->ring) {
         if (r.host)
             (void)hipHostFree(r.host);
