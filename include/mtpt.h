@@ -237,9 +237,14 @@ int mtpt_pool_create(size_t hbm_budget, int32_t max_slots, void* hip_stream,
 
 /* Admit a sim (params, pos and mass as for mtpt_create) that will run
  * n_steps (>= 1) steps; *ticket identifies it.  Its bytes are those of
- * mtpt_sim_bytes plus n_species * n * 8 of result staging.  Returns
- * MTPT_E_NOMEM when the slots or the budget cannot hold it now (retry after
- * a result has been collected); other errors as mtpt_create. */
+ * mtpt_sim_bytes plus n_species * n * 8 of result staging.  pos and mass are
+ * read before the call returns (into pinned staging owned by the pool); the
+ * upload and the set-up binning are enqueued behind the ticks in flight and
+ * the call does not wait for them (it waits only when all four staging
+ * buffers still have copies in flight).  Returns MTPT_E_NOMEM when the slots
+ * or the budget cannot hold it now (retry after a result has been
+ * collected); other errors as mtpt_create (device errors of the enqueued
+ * work surface at a later synchronising call). */
 int mtpt_pool_admit(mtpt_pool* pool, const mtpt_params* params, const double* pos,
                     const double* mass, int64_t n_steps, int64_t* ticket);
 
@@ -248,17 +253,22 @@ int mtpt_pool_admit(mtpt_pool* pool, const mtpt_params* params, const double* po
  * Returns without waiting. */
 int mtpt_pool_tick(mtpt_pool* pool, int32_t* n_completed);
 
-/* 1 in *done if the ticket's sim has taken all its steps (synchronises
- * then), else 0.  MTPT_E_ARG for an unknown ticket. */
+/* 1 in *done if the ticket's sim has taken all its steps on the device,
+ * else 0 (a query of the event behind its last step: it does not wait).
+ * MTPT_E_ARG for an unknown ticket. */
 int mtpt_pool_done(mtpt_pool* pool, int64_t ticket, int32_t* done);
 
-/* Counters and totals of an admitted sim (see mtpt_stats_t).  Synchronises.
- * MTPT_E_ARG for an unknown ticket. */
+/* Counters and totals of an admitted sim (see mtpt_stats_t).  Synchronises:
+ * for a finished sim only with its own last step (the copy runs on a second
+ * stream of the pool), else with the pool's stream.  MTPT_E_ARG for an
+ * unknown ticket. */
 int mtpt_pool_stats(mtpt_pool* pool, int64_t ticket, mtpt_stats_t* out);
 
 /* Copy a finished sim's masses (as mtpt_masses: host FP64 [n_species][n],
  * original order) into mass_out and free its slot and memory; the ticket is
- * invalid afterwards.  Synchronises.  MTPT_E_STATE if not finished,
+ * invalid afterwards.  Synchronises with the sim's last step only (the
+ * export runs on a second stream of the pool; the ticks of the other sims
+ * keep running).  MTPT_E_STATE if its last step is not enqueued yet,
  * MTPT_E_ARG for an unknown ticket. */
 int mtpt_pool_result(mtpt_pool* pool, int64_t ticket, double* mass_out);
 
