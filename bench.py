@@ -32,23 +32,29 @@ HBM_PEAK_GBS = 8000.0
 VALU_PEAK_GOPS = 256 * 64 * 2.4e9 / 1e9    # VALU lane-slots/s: 256 CUs x 64 lanes x 2.4 GHz
 
 
-def step_bytes(dim: int, ns: int, tsz: int, msz: int) -> float:
+def step_bytes(dim: int, ns: int, tsz: int, msz: int, moving: bool = True) -> float:
     """Algorithmic HBM bytes per particle and step of the whole method, with
     the walk fused into the transfer pass: positions p = tsz bytes per
     coordinate, masses q = msz per species, row sums s = tsz, pid 4:
     B = 5 d p + 4 S q + 2 s + 8 (positions read and written by the sort, read
     by the row sums, read by the transfer and written walked; masses read and
     written by the sort and by the transfer; row sums written and read; pid
-    read and written by the sort)."""
+    read and written by the sort).  Particles that never move keep their
+    order and their row sums, so a step of such a sim is the transfer alone:
+    B = d p + s + 2 S q."""
+    if not moving:
+        return dim * tsz + tsz + 2.0 * ns * msz
     return 5.0 * dim * tsz + 4.0 * ns * msz + 2.0 * tsz + 8.0
 
 
-def algorithmic_bytes(kernel: str, n: int, dim: int, ns: int, tsz: int, msz: int, ncells: int) -> float:
+def algorithmic_bytes(kernel: str, n: int, dim: int, ns: int, tsz: int, msz: int, ncells: int,
+                      moving: bool = True) -> float:
     """The kernel's share of the method's bytes (step_bytes), per launch:
     place   the sort: positions, masses and pid read and written (2dp + 2Sq + 8)
     rowsum  positions read, row sums written (dp + s)
     transfer positions and row sums read, masses read and written, walked
-            positions written (2dp + s + 2Sq)
+            positions written (2dp + s + 2Sq; dp + s + 2Sq when the
+            particles do not move)
     The shares add up to step_bytes; every other kernel (histogram scan,
     scatter, finalize) and every other byte (neighbour bits, recorded
     windows, stored jumps, cell ids and slots, halo re-reads) is overhead of
@@ -57,12 +63,13 @@ def algorithmic_bytes(kernel: str, n: int, dim: int, ns: int, tsz: int, msz: int
     share = {
         "place": 2 * pos + 2 * ns * msz + 8,
         "rowsum": pos + tsz,
-        "transfer": 2 * pos + tsz + 2 * ns * msz,
+        "transfer": (2 if moving else 1) * pos + tsz + 2 * ns * msz,
     }
     return float(share.get(kernel, 0) * n)
 
 
-def overhead_bytes(kernel: str, n: int, dim: int, ns: int, tsz: int, msz: int, ncells: int) -> dict:
+def overhead_bytes(kernel: str, n: int, dim: int, ns: int, tsz: int, msz: int, ncells: int,
+                   moving: bool = True) -> dict:
     """Bytes a launch moves beyond its algorithmic share, by structure (one
     read or write each; the measured traffic adds halo re-reads and partial
     cache lines)."""
@@ -74,8 +81,8 @@ def overhead_bytes(kernel: str, n: int, dim: int, ns: int, tsz: int, msz: int, n
     pos = dim * tsz
     per = {
         "rowsum": {"neighbour_bits": masks, "row_windows": wins},
-        "transfer": {"neighbour_bits": masks, "row_windows": wins, "stored_jumps": pos,
-                     "cell_and_slot": 8},
+        "transfer": ({"neighbour_bits": masks, "row_windows": wins, "stored_jumps": pos,
+                      "cell_and_slot": 8} if moving else {"neighbour_bits": masks, "row_windows": wins}),
         "place": {"perm": 4, "cell_offsets": 8, "stored_jumps": pos},
         "scatter": {"cell_and_slot": 8, "perm": 4},
     }.get(kernel, {})
@@ -144,8 +151,9 @@ def run_path(mt, W, precision: int, steps: int, warmup: int, profile_steps: int 
 #   walk     per particle in the transfer pass: jump add, reflection test
 #            and cell index, 10 per dimension (the generator runs in the
 #            place pass)
-def algorithmic_slots(kernel: str, n: int, pairs: int, dim: int, ns: int, prec: str) -> float:
-    walk = 10.0 * dim
+def algorithmic_slots(kernel: str, n: int, pairs: int, dim: int, ns: int, prec: str,
+                      moving: bool = True) -> float:
+    walk = 10.0 * dim if moving else 0.0
     if kernel == "rowsum":
         per = 3 * dim + 26.0 if prec == "fp64" else 2 * dim + 7.0
         return pairs * per
@@ -158,7 +166,7 @@ def algorithmic_slots(kernel: str, n: int, pairs: int, dim: int, ns: int, prec: 
     return 0.0
 
 
-def roofline(res, dim, ns, tsz, msz, n, prec="fp32w"):
+def roofline(res, dim, ns, tsz, msz, n, prec="fp32w", moving=True):
     """The dominant kernel against both rooflines (bound: the one with the
     longer ideal time), plus the whole step on the method's bytes."""
     phases = res["phases"]
@@ -169,13 +177,13 @@ def roofline(res, dim, ns, tsz, msz, n, prec="fp32w"):
     avg_s = ms_total / launches / 1e3
     common = {"kernel": name, "avg_launch_us": round(avg_s * 1e6, 2),
               "phase_ms_per_step": {k: round(v[0] / v[1], 4) for k, v in phases.items()}}
-    byt = algorithmic_bytes(name, n, dim, ns, tsz, msz, res["n_cells"])
+    byt = algorithmic_bytes(name, n, dim, ns, tsz, msz, res["n_cells"], moving)
     hbm = byt / avg_s / 1e9
     out = {**common, "bound": "hbm", "achieved": round(hbm, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
            "frac": round(hbm / HBM_PEAK_GBS, 4), "traffic": None, "bytes_per_launch": byt,
-           "overhead_bytes_per_launch": overhead_bytes(name, n, dim, ns, tsz, msz, res["n_cells"])}
+           "overhead_bytes_per_launch": overhead_bytes(name, n, dim, ns, tsz, msz, res["n_cells"], moving)}
     if name in ("rowsum", "transfer"):
-        slots = algorithmic_slots(name, n, res["pairs_per_step"], dim, ns, prec)
+        slots = algorithmic_slots(name, n, res["pairs_per_step"], dim, ns, prec, moving)
         alu = slots / avg_s / 1e9
         out["ops_per_launch"] = slots
         out["alu_frac"] = round(alu / VALU_PEAK_GOPS, 4)
@@ -184,10 +192,10 @@ def roofline(res, dim, ns, tsz, msz, n, prec="fp32w"):
             out.update({"bound": "alu", "achieved": round(alu, 1), "peak": VALU_PEAK_GOPS,
                         "unit": "Gop/s", "frac": round(alu / VALU_PEAK_GOPS, 4)})
     # the whole step: the method's bytes per particle-step over the step time
-    sb = step_bytes(dim, ns, tsz, msz) * n
+    sb = step_bytes(dim, ns, tsz, msz, moving) * n
     step_s = res["ms_per_step"] / 1e3
     out["step_bytes"] = sb
-    out["step_bytes_per_particle"] = step_bytes(dim, ns, tsz, msz)
+    out["step_bytes_per_particle"] = step_bytes(dim, ns, tsz, msz, moving)
     out["step_achieved_gbs"] = round(sb / step_s / 1e9, 1)
     out["step_frac"] = round(sb / step_s / 1e9 / HBM_PEAK_GBS, 4)
     return out
@@ -245,13 +253,19 @@ def cpu_baseline(W, workload: str = "react3d", steps: int = 1):
     from oracle import oracle as O
     threads = O.max_threads()
     w = W.make(workload, precision=W.FP32W_FP64ACC)
+    if w.params.n <= 100_000:
+        steps = w.steps                            # a small workload runs whole
     t0 = time.perf_counter()
     r = O.run(w.params, w.x0, w.m0, steps, threads=threads)
     dt = time.perf_counter() - t0
+    p = w.params
+    parts = (["walk"] if p.d_rw > 0.0 or any(v != 0.0 for v in p.vel) else []) + \
+        ["K-D tree search", "transfer"] + (["reaction"] if p.k_react > 0.0 else [])
+    which = f"all {steps} steps" if steps == w.steps else f"first {steps} step(s)"
     return {"value": float(r.pairs.sum()) / dt, "unit": "pair-updates/s", "cores": int(threads),
             "kind": "oracle",
-            "sample": f"first {steps} step(s) of the full {w.params.n:.3g}-particle {workload} workload "
-                      f"(walk, K-D tree search, transfer, reaction), {int(r.pairs.sum())} pair-updates "
+            "sample": f"{which} of the full {p.n:.3g}-particle {workload} workload "
+                      f"({', '.join(parts)}), {int(r.pairs.sum())} pair-updates "
                       f"in {dt:.1f} s on {threads} threads"}
 
 
@@ -292,6 +306,9 @@ WORKLOAD_TEXT = {
                "A+B->C mass-based reaction after each transfer, k=1",
     "adv2d": "adv2d: rw2d with a drift velocity v=(1, 0.5) (advection-dispersion), N=4e6 in "
              "[0,2000]^2, 100 steps",
+    "plain2d": "plain2d: 2-d MTPT, pure mass transfer (no random walk), N=1e4 in [0,100]^2, D_MT=1, "
+               "dt=0.1, psi=3*sqrt(4*D_MT*dt), 50 steps, m=1 for x<50 else 0 (latency-bound: the "
+               "step p50/p99 are its figures)",
     "aniso2d": "aniso2d: rw2d with a rotated dispersion tensor (principal values 2D and D/2, axes at "
                "30 degrees; walk and mass "
                "transfer), N=4e6 in [0,2000]^2, 100 steps",
@@ -307,7 +324,7 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--workload", default="react3d",
-                    choices=["react3d", "rw2d", "rw3d", "adv2d", "aniso2d", "serve"],
+                    choices=["react3d", "rw2d", "rw3d", "adv2d", "aniso2d", "plain2d", "serve"],
                     help="react3d (the largest single-GPU workload) is the benchmark line; the "
                          "others are reported the same way")
     ap.add_argument("--requests", type=int, default=120, help="serving mix size (--workload serve)")
@@ -360,18 +377,20 @@ def main():
         "mass_drift": r32["drift"],
     }
     ns = p.n_species
-    out["roofline"] = roofline(r32, p.dim, ns, 4, 8, p.n, "fp32w")
+    moving = p.d_rw > 0.0 or any(v != 0.0 for v in p.vel)
+    out["roofline"] = roofline(r32, p.dim, ns, 4, 8, p.n, "fp32w", moving)
     if out["roofline"]:
         out["roofline"]["traffic"] = traffic_from_profile(out["roofline"]["kernel"], workload, "fp32w")
     if workload == "rw3d":
         rk = run_path(mt, W, W.FP32_KAHAN, args.steps, args.warmup, workload=workload)
         out["kahan_path"] = {"value": rk["value"], "ms_per_step": rk["ms_per_step"],
                              "p50_step_ms": rk["p50_ms"], "p99_step_ms": rk["p99_ms"],
-                             "mass_drift": rk["drift"], "roofline": roofline(rk, p.dim, ns, 4, 4, p.n, "kahan")}
+                             "mass_drift": rk["drift"],
+                             "roofline": roofline(rk, p.dim, ns, 4, 4, p.n, "kahan", moving)}
     if not args.no_fp64:
         r64 = run_path(mt, W, W.FP64, args.steps, args.warmup, workload=workload)
         print(f"fp64 path: {r64['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
-        rf = roofline(r64, p.dim, ns, 8, 8, p.n, "fp64")
+        rf = roofline(r64, p.dim, ns, 8, 8, p.n, "fp64", moving)
         if rf:
             rf["traffic"] = traffic_from_profile(rf["kernel"], workload, "fp64")
         out["fp64_path"] = {"value": r64["value"], "ms_per_step": r64["ms_per_step"],

@@ -31,6 +31,12 @@
  *   - Determinism: the same params, inputs and seed give bit-identical
  *     results run to run, across a resume at start_step, and alone versus
  *     inside a pool.
+ *   - Environment: MTPT_MIN_TILES (a whole number in [1, 2^20], default 256)
+ *     is the fewest tiles a sim's mass-transfer passes are cut into, read at
+ *     create and at admission; a sim whose throughput-sized tiles would be
+ *     fewer gets smaller ones, so a small sim's step spreads over the chip.
+ *     Positions, masses and pair counts do not depend on it; the FP64 totals
+ *     only through the grouping of their partial sums.
  */
 #ifndef MTPT_H
 #define MTPT_H

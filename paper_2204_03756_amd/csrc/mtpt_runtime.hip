@@ -14,6 +14,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <deque>
 #include <map>
@@ -226,6 +227,21 @@ int validate(const mtpt_params* p)
 
 double psi_of(const mtpt_params& p) { return p.psi > 0 ? p.psi : 3.0 * std::sqrt(4.0 * p.d_mt * p.dt); }
 
+// Fewest tiles of a sim's mass-transfer passes: MTPT_MIN_TILES from the
+// environment when it holds a whole number in [1, 2^20], else 256 (one tile
+// per compute unit).  1 keeps the throughput shape at every size.
+int64_t tile_min_tiles()
+{
+    const char* e = std::getenv("MTPT_MIN_TILES");
+    if (e && *e) {
+        char* end = nullptr;
+        const long long v = std::strtoll(e, &end, 10);
+        if (end && *end == '\0' && v >= 1 && v <= (1ll << 20))
+            return v;
+    }
+    return 256;
+}
+
 Plan make_plan(const mtpt_params& p)
 {
     Plan q;
@@ -276,9 +292,17 @@ Plan make_plan(const mtpt_params& p)
     // particle: wave passes (64 lanes; a wave with no particle left leaves)
     // over the own particles (with a margin of two standard deviations of
     // their count), staging of the halo and a fixed setup, in units of one
-    // lane's candidate loop.
+    // lane's candidate loop.  A sim too small to give every compute unit a
+    // tile that way is cut into at least min_tiles tiles (or one tile per
+    // cell): its step time is then the time of one small tile, not that of a
+    // few large tiles on a mostly idle chip.
     {
         const double rho_c = static_cast<double>(q.n) / static_cast<double>(q.ncells);
+        const int64_t min_tiles = tile_min_tiles();
+        auto tiles_of = [&](int x, int y, int z) {
+            return static_cast<int64_t>((q.nc[0] + x - 1) / x) * ((q.nc[1] + y - 1) / y) *
+                   (q.dim == 3 ? (q.nc[2] + z - 1) / z : 1);
+        };
 #ifndef MTPT_TILE_OWN
 #define MTPT_TILE_OWN 640.0
 #endif
@@ -294,7 +318,8 @@ Plan make_plan(const mtpt_params& p)
                 const int tt = static_cast<int>(std::lround(std::sqrt(cells_own)));
                 tx = std::max(1, std::min(tt, std::min(q.nc[0], tile_max(2, 0))));
                 ty = std::max(1, std::min(tt, std::min(q.nc[1], tile_max(2, 1))));
-                while ((tx + 2.0) * (ty + 2.0) * rho_c > cap && (tx > 1 || ty > 1)) {
+                while (((tx + 2.0) * (ty + 2.0) * rho_c > cap || tiles_of(tx, ty, 1) < min_tiles) &&
+                       (tx > 1 || ty > 1)) {
                     if (tx >= ty)
                         --tx;
                     else
@@ -306,7 +331,8 @@ Plan make_plan(const mtpt_params& p)
                     for (int y = 1; y <= std::min(q.nc[1], tile_max(3, 1)); ++y)
                         for (int x = 1; x <= std::min(q.nc[0], tile_max(3, 0)); ++x) {
                             const double halo = (x + 2.0) * (y + 2.0) * (z + 2.0) * rho_c;
-                            if (halo > cap && !(x == 1 && y == 1 && z == 1))
+                            const bool unit = x == 1 && y == 1 && z == 1;
+                            if ((halo > cap || tiles_of(x, y, z) < min_tiles) && !unit)
                                 continue;
                             const double own = std::max(1e-9, x * y * static_cast<double>(z) * rho_c);
                             const double passes = std::ceil((own + 2.0 * std::sqrt(own)) / MTPT_TILE_LANES);

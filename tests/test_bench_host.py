@@ -19,6 +19,19 @@ def test_step_bytes_follow_the_method():
     assert bench.step_bytes(2, 1, 4, 8) == 88.0
 
 
+def test_static_step_is_the_transfer_alone():
+    # particles that never move keep order and row sums: x read, s read,
+    # masses read and written -- 2-d FP64 one species: 16 + 8 + 16 = 40 B
+    assert bench.step_bytes(2, 1, 8, 8, moving=False) == 40.0
+    assert bench.algorithmic_bytes("transfer", 100, 2, 1, 8, 8, 50, moving=False) == 40.0 * 100
+    assert bench.algorithmic_slots("transfer", 10, 100, 2, 1, "fp32w", moving=False) == 100 * 20
+    o = bench.overhead_bytes("transfer", 100, 2, 1, 8, 8, 50, moving=False)
+    assert "stored_jumps" not in o and "cell_and_slot" not in o
+    r = bench.roofline(_res({"transfer": 0.01}, 150_000, 2_500, 0.02), 2, 1, 8, 8, 10_000, "fp64",
+                       moving=False)
+    assert r["step_bytes"] == 40.0 * 10_000 and r["bytes_per_launch"] == 40.0 * 10_000
+
+
 def test_kernel_shares_add_up_to_the_step():
     # the three passes' shares of the method's bytes are the whole step
     for dim, ns, tsz, msz in ((2, 1, 4, 8), (3, 3, 4, 8), (3, 3, 8, 8), (3, 1, 4, 4)):

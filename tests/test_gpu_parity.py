@@ -46,6 +46,26 @@ def test_rw3d_small(mt, oracle, prec):
     check_parity(mt, oracle, w, w.steps)
 
 
+@pytest.mark.parametrize("case,prec", [("rw2d", W.FP32W_FP64ACC), ("rw3d", W.FP64),
+                                       ("react3d", W.FP32W_FP64ACC), ("plain2d", W.FP64)])
+def test_throughput_tile_shape_at_small_sizes(mt, oracle, monkeypatch, case, prec):
+    """The tile shapes large sims get (MTPT_MIN_TILES=1: no minimum tile
+    count), on sims small enough for the oracle that would otherwise be cut
+    into at least 256 tiles."""
+    monkeypatch.setenv("MTPT_MIN_TILES", "1")
+    w = {"rw2d": lambda: W.rw2d(n=40_000 + 37, steps=6, precision=prec),
+         "rw3d": lambda: W.rw3d(n=30_000 + 101, steps=5, precision=prec, n_src=50),
+         "react3d": lambda: W.react3d(n=40_000 + 3, steps=4, precision=prec),
+         "plain2d": lambda: W.plain2d(n=20_000, steps=20, precision=prec)}[case]()
+    say(f"  throughput tile shape {case} {PREC_NAMES[prec]} n={w.params.n}")
+    m1, x1, st1, _ = check_parity(mt, oracle, w, w.steps)
+    # the tile shape changes neither positions nor masses nor pair counts
+    monkeypatch.setenv("MTPT_MIN_TILES", "256")
+    m2, x2, st2 = gpu_run(mt, w, w.steps)
+    assert np.array_equal(m1, m2) and np.array_equal(x1, x2)
+    assert st1["pairs_total"] == st2["pairs_total"]
+
+
 @pytest.mark.parametrize("prec", [W.FP64, W.FP32W_FP64ACC, W.FP32_KAHAN])
 def test_react3d_small(mt, oracle, prec):
     w = W.react3d(n=20_000 + 3, steps=6, precision=prec)
