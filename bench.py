@@ -13,6 +13,10 @@ is reported under ``serving``.
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
                     [--no-cpu] [--no-fp64] [--no-serve]
 
+Workloads: react3d (the default and the benchmark line), rw2d, rw3d, adv2d, aniso2d, plain2d (the
+latency-bound 1e4-particle static workload, whose figures are the step p50/p99), serve (the
+serving mix alone).
+
 Prints one JSON line.  ``roofline`` prices the dominant kernel on its share
 of the method's algorithmic bytes (device-side event timings of each
 launch), and the whole step on the method's bytes per particle-step
