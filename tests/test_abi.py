@@ -114,3 +114,32 @@ def test_plan_bytes_scale_with_n(lib):
     # larger cells, so fewer bytes of per-cell tables
     pt = W.replace(big, disp=W.rotated_tensor([4.0, 1.0], [0.3]))
     assert mtpt.mtpt_sim_bytes(pt) < big_b
+
+
+def test_minimum_tile_count_from_the_environment(lib, monkeypatch):
+    # the 1e4-particle plain 2-d sim (2704 cells) has 16 throughput-sized
+    # transfer tiles; the default minimum cuts it into at least 256, whose
+    # per-tile partial sums (3 x 8 B each) the plan then holds
+    p = W.plain2d().params
+    monkeypatch.setenv("MTPT_MIN_TILES", "1")
+    few = mtpt.mtpt_sim_bytes(p)
+    monkeypatch.delenv("MTPT_MIN_TILES")
+    dflt = mtpt.mtpt_sim_bytes(p)
+    assert dflt > few
+    monkeypatch.setenv("MTPT_MIN_TILES", "256")
+    assert mtpt.mtpt_sim_bytes(p) == dflt
+    # anything but a whole number in [1, 2^20] keeps the default
+    for bad in ("", "0", "-4", "abc", "12x", str(2 ** 20 + 1)):
+        monkeypatch.setenv("MTPT_MIN_TILES", bad)
+        assert mtpt.mtpt_sim_bytes(p) == dflt, bad
+    # one tile per cell at most
+    monkeypatch.setenv("MTPT_MIN_TILES", str(2 ** 20))
+    most = mtpt.mtpt_sim_bytes(p)
+    monkeypatch.setenv("MTPT_MIN_TILES", "2704")
+    assert mtpt.mtpt_sim_bytes(p) == most > dflt
+    # a large sim keeps its throughput tiles
+    big = W.rw2d().params
+    monkeypatch.setenv("MTPT_MIN_TILES", "1")
+    b1 = mtpt.mtpt_sim_bytes(big)
+    monkeypatch.delenv("MTPT_MIN_TILES")
+    assert mtpt.mtpt_sim_bytes(big) == b1
