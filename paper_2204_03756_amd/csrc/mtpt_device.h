@@ -514,16 +514,31 @@ __device__ __forceinline__ void scan_reduce_body(const uint32_t* in, const uint3
         bsum[blk] = t;
 }
 
+// Exclusive scan of the nb tile totals in place, by one workgroup: each
+// thread takes 16 consecutive totals per round (its loads in flight
+// together), so a round covers 4096 totals.
 __device__ __forceinline__ void scan_top_body(uint32_t* bsum, uint32_t nb)
 {
+    constexpr uint32_t kTop = 16;
     uint32_t carry = 0;
-    for (uint32_t base = 0; base < nb; base += kBlock) {
-        const uint32_t idx = base + threadIdx.x;
-        const uint32_t v = idx < nb ? bsum[idx] : 0u;
+    for (uint32_t base = 0; base < nb; base += kBlock * kTop) {
+        const uint32_t i0 = base + threadIdx.x * kTop;
+        uint32_t v[kTop];
+#pragma unroll
+        for (uint32_t q = 0; q < kTop; ++q)
+            v[q] = i0 + q < nb ? bsum[i0 + q] : 0u;
+        uint32_t sum = 0;
+#pragma unroll
+        for (uint32_t q = 0; q < kTop; ++q)
+            sum += v[q];
         uint32_t tot;
-        const uint32_t ex = block_excl_scan(v, &tot);
-        if (idx < nb)
-            bsum[idx] = carry + ex;
+        uint32_t run = carry + block_excl_scan(sum, &tot);
+#pragma unroll
+        for (uint32_t q = 0; q < kTop; ++q) {
+            if (i0 + q < nb)
+                bsum[i0 + q] = run;
+            run += v[q];
+        }
         carry += tot;
     }
 }
