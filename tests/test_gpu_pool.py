@@ -158,3 +158,50 @@ def test_pool_admission_budget_and_slots(mt):
         assert mt.mtpt_pool_admit(pool, r.params, r.x0, r.m0, 2) is None   # no slot
     finally:
         mt.mtpt_pool_destroy(pool)
+
+
+def test_pool_batches_every_kernel_variant(mt, oracle):
+    """One pool holding a sim of every kind it batches separately -- static
+    and moving, 2-d and 3-d, the three precisions, one and three species
+    (with the reaction), a drift, dispersion tensors -- so that each group's
+    batched kernels run beside the others': every result equals the same sim
+    run alone bit for bit, and the oracle within its precision's bar."""
+    from gpu_helpers import TOL, normwise
+    t3 = W.rotated_tensor([3.0, 1.0, 0.5], [0.3, 0.2, 0.1])
+    r3 = W.react3d(n=20_000 + 3, steps=5, precision=W.FP32W_FP64ACC)
+    d3 = W.rw3d(n=15_000 + 9, steps=5, precision=W.FP64, n_src=20)
+    ws = [
+        W.plain2d(n=5000, steps=6, precision=W.FP64),
+        W.plain2d(n=7000, steps=6, precision=W.FP32W_FP64ACC),
+        r3,
+        W.react3d(n=12_000 + 1, steps=4, precision=W.FP64),
+        W.react3d(n=12_000 + 5, steps=4, precision=W.FP32_KAHAN),
+        W.aniso2d(n=20_000 + 7, steps=5, precision=W.FP32_KAHAN),
+        W.adv2d(n=20_000 + 11, steps=5, precision=W.FP32W_FP64ACC),
+        W.Workload("drift3d", W.replace(d3.params, vel=[0.5, -0.3, 0.2]), d3.x0, d3.m0, 5, {}),
+        W.Workload("tens_react3d", W.replace(r3.params, disp=t3, seed=0x4D54505477), r3.x0, r3.m0, 4, {}),
+    ]
+    reqs = [W.Request(900 + i, 0.0, w.params, w.x0, w.m0, w.steps) for i, w in enumerate(ws)]
+    pool = mt.mtpt_pool_create(0, len(reqs))
+    results = {}
+    try:
+        active = {}
+        for r in reqs:
+            t = mt.mtpt_pool_admit(pool, r.params, r.x0, r.m0, r.steps)
+            assert t is not None
+            active[t] = r
+        while active:
+            mt.mtpt_pool_tick(pool)
+            for t in list(active):
+                if mt.mtpt_pool_done(pool, t):
+                    r = active.pop(t)
+                    results[r.rid] = mt.mtpt_pool_result(pool, t, r.params.n, r.params.n_species)
+    finally:
+        mt.mtpt_pool_destroy(pool)
+    for w, r in zip(ws, reqs):
+        a = alone(mt, r)
+        assert np.array_equal(a, results[r.rid]), f"{w.name} differs alone vs in the mix"
+        ref = oracle.run(r.params, r.x0, r.m0, r.steps)
+        err = normwise(results[r.rid], ref.m)
+        print(f"  pool variant {w.name} prec {r.params.precision}: normwise {err:.3e}", flush=True)
+        assert err <= TOL[r.params.precision], w.name
