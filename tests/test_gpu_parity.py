@@ -220,6 +220,28 @@ def test_deterministic_and_resume(mt, prec):
     assert np.array_equal(a, c) and np.array_equal(xa, xc)
 
 
+@pytest.mark.parametrize("kind,prec", [("react3d", W.FP32W_FP64ACC), ("react3d", W.FP64),
+                                       ("react3d", W.FP32_KAHAN), ("drift_tens3d", W.FP32W_FP64ACC)])
+def test_resume_bitwise_variants(mt, kind, prec):
+    """Three species with the reaction (whose masses the row-sum pass moves
+    into the sorted order), and a drift with a rotated tensor: steps taken in
+    chunks, or resumed at start_step from the exported state, equal one run."""
+    if kind == "react3d":
+        w = W.react3d(n=20_000 + 3, steps=6, precision=prec)
+    else:
+        w0 = W.rw3d(n=20_000 + 7, steps=6, precision=prec, n_src=20)
+        w = W.Workload(kind, W.replace(w0.params, vel=[0.4, -0.2, 0.3],
+                                       disp=W.rotated_tensor([2.0, 1.0, 0.5], [0.4, 0.1, 0.2])),
+                       w0.x0, w0.m0, 6, {})
+    a, xa, _ = gpu_run(mt, w, 6)
+    b, xb, _ = gpu_run(mt, w, 6, chunks=[1, 2, 3])
+    assert np.array_equal(a, b) and np.array_equal(xa, xb)
+    h, xh, _ = gpu_run(mt, w, 3)
+    p2 = W.Params(**{**w.params.as_dict(), "start_step": 3})
+    c, xc, _ = gpu_run(mt, W.Workload(w.name, p2, xh, h, 3), 3)
+    assert np.array_equal(a, c) and np.array_equal(xa, xc)
+
+
 def test_static_resume_bitwise(mt):
     w = W.plain2d(n=5000, steps=10)
     a, _, _ = gpu_run(mt, w, 10)
