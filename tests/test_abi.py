@@ -143,3 +143,25 @@ def test_minimum_tile_count_from_the_environment(lib, monkeypatch):
     b1 = mtpt.mtpt_sim_bytes(big)
     monkeypatch.delenv("MTPT_MIN_TILES")
     assert mtpt.mtpt_sim_bytes(big) == b1
+
+
+def test_plan_at_the_largest_n(lib):
+    """n = 2^31 - 256, the largest the ABI accepts, plans without overflow
+    (cells capped at 2^30 and at ~4 per particle; 64-bit offsets), in 2-d
+    and in 3-d with three species; one particle more is refused."""
+    nmax = 2 ** 31 - 256
+    for dim, ns, prec in ((2, 1, W.FP32W_FP64ACC), (3, 3, W.FP64), (3, 1, W.FP32_KAHAN)):
+        L = float(nmax) ** (1.0 / dim)
+        hi = [L] * dim + [0.0] * (3 - dim)
+        p = W.Params(dim=dim, n=nmax, lo=[0.0, 0.0, 0.0], hi=hi, d_rw=0.3, d_mt=0.7, dt=0.05,
+                     n_species=ns, k_react=1.0 if ns == 3 else 0.0, precision=prec)
+        b = mtpt.mtpt_sim_bytes(p)
+        per = b / nmax
+        assert 40 < per < 400, (dim, ns, prec, per)
+        half = mtpt.mtpt_sim_bytes(W.replace(p, n=nmax // 2))
+        assert 1.8 < b / half < 2.2
+        # a box far too large for cells of side psi: the grid is coarsened
+        sparse = mtpt.mtpt_sim_bytes(W.replace(p, hi=[1e7] * dim + [0.0] * (3 - dim)))
+        assert sparse / nmax < 2 * per
+        with pytest.raises(mtpt.MtptError):
+            mtpt.mtpt_sim_bytes(W.replace(p, n=nmax + 1))
