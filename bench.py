@@ -99,9 +99,9 @@ def overhead_bytes(kernel: str, n: int, dim: int, ns: int, tsz: int, msz: int, n
 
 
 def run_path(mt, W, precision: int, steps: int, warmup: int, profile_steps: int = 5,
-             workload: str = "rw2d"):
+             workload: str = "rw2d", n=None):
     import torch
-    w = W.make(workload, precision=precision, steps=steps)
+    w = W.make(workload, precision=precision, steps=steps, **({"n": n} if n else {}))
     stream = torch.cuda.Stream()
     alloc = mt.TorchAllocator("cuda:0")
     with torch.cuda.stream(stream):
@@ -251,12 +251,12 @@ def profile_driver(mt, W, workload: str, precision: int, steps: int):
           flush=True)
 
 
-def cpu_baseline(W, workload: str = "react3d", steps: int = 1):
+def cpu_baseline(W, workload: str = "react3d", steps: int = 1, n=None):
     """The oracle on the host cores, on a bounded sample: the first step(s)
     of the same workload (FP32 position state, as the timed path)."""
     from oracle import oracle as O
     threads = O.max_threads()
-    w = W.make(workload, precision=W.FP32W_FP64ACC)
+    w = W.make(workload, precision=W.FP32W_FP64ACC, **({"n": n} if n else {}))
     if w.params.n <= 100_000:
         steps = w.steps                            # a small workload runs whole
     t0 = time.perf_counter()
@@ -331,6 +331,10 @@ def main():
                     choices=["react3d", "rw2d", "rw3d", "adv2d", "aniso2d", "plain2d", "serve"],
                     help="react3d (the largest single-GPU workload) is the benchmark line; the "
                          "others are reported the same way")
+    ap.add_argument("--n", type=int, default=None,
+                    help="particles (default: the workload's own size); the box is scaled to keep "
+                         "the workload's density, e.g. --n 4170000 for one GPU's share of the 3-d "
+                         "reacting workload split over eight")
     ap.add_argument("--requests", type=int, default=120, help="serving mix size (--workload serve)")
     ap.add_argument("--serve-requests", type=int, default=48, help="serving mix size on the benchmark line")
     ap.add_argument("--profile-driver", action="store_true",
@@ -363,7 +367,7 @@ def main():
         return
 
     workload = args.workload
-    r32 = run_path(mt, W, W.FP32W_FP64ACC, args.steps, args.warmup, workload=workload)
+    r32 = run_path(mt, W, W.FP32W_FP64ACC, args.steps, args.warmup, workload=workload, n=args.n)
     print(f"fp32w path: {r32['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
     w = r32["w"]
     p = w.params
@@ -373,7 +377,8 @@ def main():
         "warmup": args.warmup, "ms_per_step": r32["ms_per_step"], "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32-weights/f64-accum",
         "data": "synthetic (seeded uniform positions, workload's initial masses)",
-        "config": {"workload": WORKLOAD_TEXT[workload],
+        "config": {"workload": WORKLOAD_TEXT[workload] + (
+                       f" -- scaled to N={p.n} at the same density" if args.n else ""),
                    "n": p.n, "dim": p.dim, "species": p.n_species, "precision": "fp32w_fp64acc",
                    "pairs_per_step": r32["pairs_per_step"], "n_cells": r32["n_cells"]},
         "create_s_pcie_inclusive": r32["create_s"],
@@ -383,19 +388,19 @@ def main():
     ns = p.n_species
     moving = p.d_rw > 0.0 or any(v != 0.0 for v in p.vel)
     out["roofline"] = roofline(r32, p.dim, ns, 4, 8, p.n, "fp32w", moving)
-    if out["roofline"]:
+    if out["roofline"] and not args.n:
         out["roofline"]["traffic"] = traffic_from_profile(out["roofline"]["kernel"], workload, "fp32w")
     if workload == "rw3d":
-        rk = run_path(mt, W, W.FP32_KAHAN, args.steps, args.warmup, workload=workload)
+        rk = run_path(mt, W, W.FP32_KAHAN, args.steps, args.warmup, workload=workload, n=args.n)
         out["kahan_path"] = {"value": rk["value"], "ms_per_step": rk["ms_per_step"],
                              "p50_step_ms": rk["p50_ms"], "p99_step_ms": rk["p99_ms"],
                              "mass_drift": rk["drift"],
                              "roofline": roofline(rk, p.dim, ns, 4, 4, p.n, "kahan", moving)}
     if not args.no_fp64:
-        r64 = run_path(mt, W, W.FP64, args.steps, args.warmup, workload=workload)
+        r64 = run_path(mt, W, W.FP64, args.steps, args.warmup, workload=workload, n=args.n)
         print(f"fp64 path: {r64['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
         rf = roofline(r64, p.dim, ns, 8, 8, p.n, "fp64", moving)
-        if rf:
+        if rf and not args.n:
             rf["traffic"] = traffic_from_profile(rf["kernel"], workload, "fp64")
         out["fp64_path"] = {"value": r64["value"], "ms_per_step": r64["ms_per_step"],
                             "p50_step_ms": r64["p50_ms"], "p99_step_ms": r64["p99_ms"],
@@ -407,7 +412,7 @@ def main():
         out["serving"] = {"workload": SERVE_TEXT, "requests": args.serve_requests,
                           "closed_loop": closed, "poisson": {**open_, "rate_per_s": rate}}
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(W, workload)
+        out["cpu_baseline"] = cpu_baseline(W, workload, n=args.n)
     print(json.dumps(out), flush=True)
 
 
