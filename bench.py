@@ -251,9 +251,11 @@ def profile_driver(mt, W, workload: str, precision: int, steps: int):
           flush=True)
 
 
-def cpu_baseline(W, workload: str = "react3d", steps: int = 1, n=None):
+def cpu_baseline(W, workload: str = "react3d", steps: int = 1, n=None, target_s: float = 10.0):
     """The oracle on the host cores, on a bounded sample: the first step(s)
-    of the same workload (FP32 position state, as the timed path)."""
+    of the same workload (FP32 position state, as the timed path) -- one
+    step, or as many as take about target_s seconds when one step is
+    quicker than half of that (at most the workload's own steps)."""
     from oracle import oracle as O
     threads = O.max_threads()
     w = W.make(workload, precision=W.FP32W_FP64ACC, **({"n": n} if n else {}))
@@ -262,13 +264,18 @@ def cpu_baseline(W, workload: str = "react3d", steps: int = 1, n=None):
     t0 = time.perf_counter()
     r = O.run(w.params, w.x0, w.m0, steps, threads=threads)
     dt = time.perf_counter() - t0
+    if dt < 0.5 * target_s and steps < w.steps:
+        steps = min(w.steps, max(steps + 1, int(math.ceil(target_s / (dt / steps)))))
+        t0 = time.perf_counter()
+        r = O.run(w.params, w.x0, w.m0, steps, threads=threads)
+        dt = time.perf_counter() - t0
     p = w.params
     parts = (["walk"] if p.d_rw > 0.0 or any(v != 0.0 for v in p.vel) else []) + \
         ["K-D tree search", "transfer"] + (["reaction"] if p.k_react > 0.0 else [])
     which = f"all {steps} steps" if steps == w.steps else f"first {steps} step(s)"
     return {"value": float(r.pairs.sum()) / dt, "unit": "pair-updates/s", "cores": int(threads),
             "kind": "oracle",
-            "sample": f"{which} of the full {p.n:.3g}-particle {workload} workload "
+            "sample": f"{which} of the {p.n:.3g}-particle {workload} workload "
                       f"({', '.join(parts)}), {int(r.pairs.sum())} pair-updates "
                       f"in {dt:.1f} s on {threads} threads"}
 
