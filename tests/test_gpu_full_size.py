@@ -42,15 +42,22 @@ def test_react3d_full_size_parity(mt, oracle, prec):
 
 
 def test_react3d_full_size_invariants(mt):
-    """3.2e7 particles, 20 steps: the transfer conserves A + C and B + C, the
-    reaction makes C, no mass goes negative."""
+    """3.2e7 particles, the workload's 200 steps: the transfer conserves
+    A + C and B + C, the reaction makes C, no mass goes negative, every
+    particle stays in the box, and the pair count stays that of the
+    uniform density."""
     w = W.react3d(precision=W.FP32W_FP64ACC)
-    m, x, st = gpu_run(mt, w, 20)
-    assert st["nonfinite"] == 0
+    m, x, st = gpu_run(mt, w, w.steps)
+    assert st["nonfinite"] == 0 and st["steps_done"] == w.steps
     ta, tb = m[0].sum() + m[2].sum(), m[1].sum() + m[2].sum()
     assert abs(ta / w.m0[0].sum() - 1) < 1e-9 and abs(tb / w.m0[1].sum() - 1) < 1e-9
     assert m[2].sum() > 0 and m.min() > -1e-12
-    say(f"  react3d 20 steps: C total {m[2].sum():.6e}")
+    assert np.all((x >= 0) & (x <= w.params.hi[0]))
+    # ordered pairs per particle: (4/3) pi psi^3 at density 1 (5.92), less
+    # the walls' share; a walk that lost uniformity would move it
+    per = st["pairs_last"] / w.params.n
+    assert 5.7 < per < 5.95, per
+    say(f"  react3d {w.steps} steps: C total {m[2].sum():.6e}, pairs/particle {per:.4f}")
 
 
 def test_rw2d_full_size_first_steps(mt, oracle):
