@@ -399,10 +399,12 @@ def main():
         out["roofline"]["traffic"] = traffic_from_profile(out["roofline"]["kernel"], workload, "fp32w")
     if workload == "rw3d":
         rk = run_path(mt, W, W.FP32_KAHAN, args.steps, args.warmup, workload=workload, n=args.n)
+        rfk = roofline(rk, p.dim, ns, 4, 4, p.n, "kahan", moving)
+        if rfk and not args.n:
+            rfk["traffic"] = traffic_from_profile(rfk["kernel"], workload, "kahan")
         out["kahan_path"] = {"value": rk["value"], "ms_per_step": rk["ms_per_step"],
                              "p50_step_ms": rk["p50_ms"], "p99_step_ms": rk["p99_ms"],
-                             "mass_drift": rk["drift"],
-                             "roofline": roofline(rk, p.dim, ns, 4, 4, p.n, "kahan", moving)}
+                             "mass_drift": rk["drift"], "roofline": rfk}
     if not args.no_fp64:
         r64 = run_path(mt, W, W.FP64, args.steps, args.warmup, workload=workload, n=args.n)
         print(f"fp64 path: {r64['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
