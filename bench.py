@@ -231,6 +231,22 @@ def traffic_from_profile(kernel: str, workload: str, precision: str):
     return k["bytes_per_launch"]
 
 
+def valu_issue_from_profile(kernel: str, workload: str, precision: str, avg_s: float):
+    """Measured VALU issue of a kernel: its VALU instructions per launch
+    (SQ_INSTS_VALU from the committed PMC summary) x 4 cycles (a wave64
+    instruction on a 16-lane SIMD) over the cycles of 1024 SIMDs at 2.4 GHz
+    during the launch time measured here; None when the kernel source changed
+    since the counters were taken or no summary covers the workload."""
+    path = os.path.join(ROOT, "profiles", f"valu_{workload}_{precision}.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    k = rec.get("kernels", {}).get(kernel)
+    if rec.get("source_sha256") != source_sha256() or k is None or avg_s <= 0:
+        return None
+    return round(k["valu_insts_per_launch"] * 4.0 / (1024 * 2.4e9 * avg_s), 4)
+
+
 def profile_driver(mt, W, workload: str, precision: int, steps: int):
     """Target of the PMC runs: a calibration copy of a known size, then a few
     steps of one workload.  Prints nothing but its own markers."""
@@ -396,7 +412,10 @@ def main():
     moving = p.d_rw > 0.0 or any(v != 0.0 for v in p.vel)
     out["roofline"] = roofline(r32, p.dim, ns, 4, 8, p.n, "fp32w", moving)
     if out["roofline"] and not args.n:
-        out["roofline"]["traffic"] = traffic_from_profile(out["roofline"]["kernel"], workload, "fp32w")
+        rf32 = out["roofline"]
+        rf32["traffic"] = traffic_from_profile(rf32["kernel"], workload, "fp32w")
+        rf32["valu_issue_frac"] = valu_issue_from_profile(rf32["kernel"], workload, "fp32w",
+                                                          rf32["avg_launch_us"] * 1e-6)
     if workload == "rw3d":
         rk = run_path(mt, W, W.FP32_KAHAN, args.steps, args.warmup, workload=workload, n=args.n)
         rfk = roofline(rk, p.dim, ns, 4, 4, p.n, "kahan", moving)

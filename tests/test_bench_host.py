@@ -91,3 +91,18 @@ def test_more_than_one_gpu_is_refused():
                        capture_output=True, text=True, timeout=120)
     assert p.returncode == 2
     assert "one GPU" in p.stderr
+
+
+def test_valu_issue_from_the_committed_counters():
+    # the dominant kernels' VALU instructions per launch come from the
+    # committed PMC summary, and only while the sources are the profiled ones
+    import json
+    rec = json.load(open(os.path.join(ROOT, "profiles", "valu_react3d_fp32w.json")))
+    k = rec["kernels"]["rowsum"]
+    v = bench.valu_issue_from_profile("rowsum", "react3d", "fp32w", k["avg_ns"] * 1e-9)
+    if rec["source_sha256"] == bench.source_sha256():
+        assert v == pytest.approx(k["valu_insts_per_launch"] * 4 / (1024 * 2.4e9 * k["avg_ns"] * 1e-9), rel=1e-3)
+        assert 0.3 < v < 1.2
+    else:
+        assert v is None
+    assert bench.valu_issue_from_profile("rowsum", "no_such_workload", "fp32w", 1e-3) is None
