@@ -296,14 +296,15 @@ def cpu_baseline(W, workload: str = "react3d", steps: int = 1, n=None, target_s:
                       f"in {dt:.1f} s on {threads} threads"}
 
 
-def serve_bench(mt, W, n_req: int, seed: int = 20220404):
+def serve_bench(mt, W, n_req: int, seed: int = 20220404, budget: int = 0):
     """The serving mix: closed-loop capacity first (all requests at t = 0),
-    then a Poisson stream at 80 % of that capacity, both through the pool."""
+    then a Poisson stream at 80 % of that capacity, both through the pool
+    (budget: its HBM bytes, 0 for 90 % of the free memory)."""
     from paper_2204_03756_amd import serve
     import torch
     alloc = mt.TorchAllocator("cuda:0")
     reqs = [W.request(i, base_seed=seed) for i in range(n_req)]
-    be = serve.PoolBackend(0, 64, allocator=alloc)
+    be = serve.PoolBackend(budget, 64, allocator=alloc)
     try:
         closed = serve.serve(be, reqs, None, realtime=True).summary()
     finally:
@@ -312,7 +313,7 @@ def serve_bench(mt, W, n_req: int, seed: int = 20220404):
     rate = 0.8 * closed["sims_per_s"]
     reqs2 = [W.request(n_req + i, base_seed=seed) for i in range(n_req)]
     arr = W.arrivals(n_req, rate, seed=seed + 1)
-    be = serve.PoolBackend(0, 64, allocator=alloc)
+    be = serve.PoolBackend(budget, 64, allocator=alloc)
     try:
         open_ = serve.serve(be, reqs2, arr, realtime=True).summary()
     finally:
@@ -360,6 +361,8 @@ def main():
                          "reacting workload split over eight")
     ap.add_argument("--requests", type=int, default=120, help="serving mix size (--workload serve)")
     ap.add_argument("--serve-requests", type=int, default=48, help="serving mix size on the benchmark line")
+    ap.add_argument("--budget-mb", type=int, default=0,
+                    help="HBM budget of the serving pool in MiB (--workload serve; 0: 90 %% of free memory)")
     ap.add_argument("--profile-driver", action="store_true",
                     help="run a calibration copy and a few steps (for rocprofv3 --pmc)")
     ap.add_argument("--precision", default="fp32w", choices=["fp64", "fp32w", "kahan"])
@@ -380,12 +383,13 @@ def main():
         return
 
     if args.workload == "serve":
-        closed, open_, rate = serve_bench(mt, W, args.requests)
+        closed, open_, rate = serve_bench(mt, W, args.requests, budget=args.budget_mb << 20)
         print(json.dumps({
             "metric": "serving mix: sims/s and p50/p99 request latency (continuous batching)",
             "value": open_["sims_per_s"], "unit": "sims/s", "n_gpus": 1,
             "higher_is_better": True, "dtype": "f32-kahan", "data": "synthetic",
-            "config": {"workload": SERVE_TEXT, "requests": args.requests, "poisson_rate_per_s": rate},
+            "config": {"workload": SERVE_TEXT, "requests": args.requests, "poisson_rate_per_s": rate,
+                       "hbm_budget_mib": args.budget_mb or None},
             "closed_loop": closed, "poisson": open_}), flush=True)
         return
 
