@@ -1,0 +1,75 @@
+"""Randomised parity: small sims drawn over the parameter space the C-ABI
+accepts -- dimension, precision, one or three species (with and without the
+reaction), static or walking particles, a drift, a rotated dispersion tensor,
+beta, an explicit or default psi, boxes off the origin of uneven sides and
+densities from sparse to dense -- each against the oracle at its precision's
+bar, positions bit for bit and pair counts exact.  The draws are seeded, so
+every run checks the same cases."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2204_03756_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+from gpu_helpers import PREC_NAMES, check_parity, load_mt, say  # noqa: E402
+
+N_CASES = 80
+
+
+@pytest.fixture(scope="module")
+def mt():
+    return load_mt()
+
+
+def draw_case(k: int) -> W.Workload:
+    rng = np.random.Generator(np.random.Philox(0x5EED0000 + k))
+    dim = int(rng.integers(2, 4))
+    prec = int(rng.integers(0, 3))
+    ns = 3 if rng.random() < 0.35 else 1
+    d_mt = float(rng.uniform(0.1, 2.0))
+    dt = float(rng.uniform(0.02, 0.2))
+    d_rw = 0.0 if rng.random() < 0.2 else float(rng.uniform(0.05, 1.5))
+    beta = float(rng.choice([0.25, 0.5, 1.0]))
+    psi_def = 3.0 * math.sqrt(4.0 * d_mt * dt)
+    psi = 0.0 if rng.random() < 0.6 else float(psi_def * rng.uniform(0.5, 1.5))
+    lo = [float(v) for v in rng.uniform(-20.0, 20.0, 3)]
+    sides = rng.uniform(4.0, 30.0, 3) * (psi if psi > 0 else psi_def)
+    hi = [lo[i] + float(sides[i]) for i in range(3)]
+    if dim == 2:
+        lo[2], hi[2] = 0.0, 0.0
+    vol = float(np.prod(sides[:dim]))
+    dens_per_cell = float(rng.choice([0.3, 1.5, 6.0, 20.0]))
+    cell_vol = (psi if psi > 0 else psi_def) ** dim
+    n = int(np.clip(dens_per_cell * vol / cell_vol, 50, 20000))
+    vel = [0.0, 0.0, 0.0]
+    if rng.random() < 0.3:
+        vel = [float(v) for v in rng.uniform(-1.0, 1.0, 3)]
+        if dim == 2:
+            vel[2] = 0.0
+    disp = [0.0] * 9
+    if rng.random() < 0.3:
+        eigs = rng.uniform(0.4, 3.0, dim).tolist()
+        ang = rng.uniform(0.0, math.pi, 1 if dim == 2 else 3).tolist()
+        disp = W.rotated_tensor(eigs, ang)
+    k_react = float(rng.choice([0.0, 0.5, 2.0])) if ns == 3 else 0.0
+    p = W.Params(dim=dim, n=n, lo=lo, hi=hi, d_rw=d_rw, d_mt=d_mt, dt=dt, beta=beta, psi=psi,
+                 k_react=k_react, n_species=ns, seed=0x4D545054A000 + k, precision=prec,
+                 vel=vel, disp=disp)
+    u = rng.random((n, dim))
+    x = np.minimum(np.asarray(lo[:dim]) + u * np.asarray(sides[:dim]), np.asarray(hi[:dim]))
+    m = rng.uniform(0.0, 1.0, (ns, n))
+    steps = int(rng.integers(1, 7))
+    return W.Workload(f"random{k}", p, x, m, steps, {})
+
+
+@pytest.mark.parametrize("k", range(N_CASES))
+def test_random_config_parity(mt, oracle, k):
+    w = draw_case(k)
+    p = w.params
+    say(f"  case {k}: d={p.dim} {PREC_NAMES[p.precision]} S={p.n_species} k={p.k_react} n={p.n} "
+        f"d_rw={p.d_rw:.3g} beta={p.beta} psi={p.psi:.3g} drift={any(v != 0 for v in p.vel)} "
+        f"tensor={any(v != 0 for v in p.disp)} steps={w.steps}")
+    check_parity(mt, oracle, w, w.steps)
