@@ -73,3 +73,32 @@ def test_random_config_parity(mt, oracle, k):
         f"d_rw={p.d_rw:.3g} beta={p.beta} psi={p.psi:.3g} drift={any(v != 0 for v in p.vel)} "
         f"tensor={any(v != 0 for v in p.disp)} steps={w.steps}")
     check_parity(mt, oracle, w, w.steps)
+
+
+def test_random_configs_in_one_pool(mt):
+    """Twenty of the draws admitted together into one pool (their kernels
+    batched by kind, their steps interleaved): every result equals the same
+    sim run alone, bit for bit."""
+    ws = [draw_case(k) for k in range(20)]
+    pool = mt.mtpt_pool_create(0, len(ws))
+    results = {}
+    try:
+        active = {}
+        for i, w in enumerate(ws):
+            t = mt.mtpt_pool_admit(pool, w.params, w.x0, w.m0, w.steps)
+            assert t is not None
+            active[t] = i
+        while active:
+            mt.mtpt_pool_tick(pool)
+            for t in list(active):
+                if mt.mtpt_pool_done(pool, t):
+                    i = active.pop(t)
+                    results[i] = mt.mtpt_pool_result(pool, t, ws[i].params.n, ws[i].params.n_species)
+    finally:
+        mt.mtpt_pool_destroy(pool)
+    alloc = mt.TorchAllocator("cuda:0")
+    for i, w in enumerate(ws):
+        with mt.Sim(w.params, w.x0, w.m0, allocator=alloc) as sim:
+            sim.step(w.steps)
+            a = sim.masses()
+        assert np.array_equal(a, results[i]), f"draw {i} differs alone vs in the pool"
