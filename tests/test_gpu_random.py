@@ -102,3 +102,22 @@ def test_random_configs_in_one_pool(mt):
             sim.step(w.steps)
             a = sim.masses()
         assert np.array_equal(a, results[i]), f"draw {i} differs alone vs in the pool"
+
+
+@pytest.mark.parametrize("k", range(0, N_CASES, 4))
+def test_random_config_hot_neighbor_sets(mt, oracle, k):
+    """Sec. 3, Eq. (1): on every fourth draw, the pairs the last step's
+    row-sum and transfer passes used equal the oracle's K-D tree sets at the
+    positions of that step, bit for bit."""
+    w = draw_case(k)
+    alloc = mt.TorchAllocator("cuda:0")
+    with mt.Sim(w.params, w.x0, w.m0, allocator=alloc) as sim:
+        sim.step(w.steps)
+        x = sim.positions()
+        hot = (sim.step_neighbors(0), sim.step_neighbors(1))
+    ref = oracle.run(w.params, w.x0, w.m0, w.steps)
+    assert np.array_equal(x, ref.x)
+    orow, ocol = oracle.neighbors(ref.x, w.params.psi_eff, "kdtree", tens=oracle.tensor_of(w.params))
+    for name, (row, col) in zip(("row-sum", "transfer"), hot):
+        assert np.array_equal(row, orow), f"draw {k}, {name} pass: row lengths differ"
+        assert np.array_equal(col, ocol), f"draw {k}, {name} pass: columns differ"
