@@ -121,3 +121,39 @@ def test_random_config_hot_neighbor_sets(mt, oracle, k):
     for name, (row, col) in zip(("row-sum", "transfer"), hot):
         assert np.array_equal(row, orow), f"draw {k}, {name} pass: row lengths differ"
         assert np.array_equal(col, ocol), f"draw {k}, {name} pass: columns differ"
+
+
+def _extreme(kind: str, prec: int) -> W.Workload:
+    rng = np.random.Generator(np.random.Philox(0x5EED1000 + len(kind)))
+    if kind == "coarse2d":      # box of 2000 psi a side, 800 particles: the grid is coarsened
+        dim, n, side, d_mt, dt = 2, 800, 2000.0 * 1.8974, 1.0, 0.1
+    elif kind == "coarse3d":
+        dim, n, side, d_mt, dt = 3, 1500, 300.0 * 1.8974, 1.0, 0.1
+    elif kind == "tiny_dt":     # psi 3e-3: thousands of cells per unit length
+        dim, n, side, d_mt, dt = 2, 6000, 0.25, 1.0, 1e-7
+    else:                       # every particle within psi of every other
+        dim, n, side, d_mt, dt = 3, 400, 1.0, 1.0, 0.5
+    hi = [side] * dim + [0.0] * (3 - dim)
+    p = W.Params(dim=dim, n=n, lo=[0.0, 0.0, 0.0], hi=hi, d_rw=0.5 * d_mt, d_mt=d_mt, dt=dt,
+                 beta=float(rng.choice([0.01, 0.5, 1.0])), seed=0x4D545054B000 + len(kind),
+                 precision=prec)
+    if kind.startswith("coarse"):
+        # clusters of 100 particles, 3 psi across, scattered over the box
+        cent = rng.random((n // 100, dim)) * (side - 10.0) + 5.0
+        x = cent[np.arange(n) // 100] + (rng.random((n, dim)) - 0.5) * 3.0 * p.psi_eff
+    else:
+        x = rng.random((n, dim)) * side
+    x = np.minimum(np.maximum(x, 0.0), side)
+    m = rng.uniform(0.0, 1.0, (1, n))
+    return W.Workload(kind, p, x, m, 3, {})
+
+
+@pytest.mark.parametrize("kind", ["coarse2d", "coarse3d", "tiny_dt", "all_pairs"])
+@pytest.mark.parametrize("prec", [W.FP64, W.FP32W_FP64ACC])
+def test_extreme_geometry_parity(mt, oracle, kind, prec):
+    """Grids coarsened far beyond psi (cells capped at about four per
+    particle), a psi of a few thousandths, and a box whose every pair is
+    within psi: parity with the oracle as everywhere else."""
+    w = _extreme(kind, prec)
+    say(f"  extreme {kind} {PREC_NAMES[prec]} n={w.params.n} psi={w.params.psi_eff:.3g}")
+    check_parity(mt, oracle, w, w.steps)
