@@ -73,3 +73,25 @@ def test_rw2d_full_size_first_steps(mt, oracle):
     assert m.min() >= -1e-15 and m.max() <= w.m0.max() * (1 + 1e-12)
     assert np.all((x >= 0) & (x <= w.params.hi[0]))
     say(f"  rw2d 100 steps: drift {st['drift']:.3e}, pairs/step {st['pairs_last']}")
+
+
+def test_long_runs_keep_the_invariants(mt):
+    """Thousands of steps (far past the workloads' 50-200): the walking 2-d
+    sim and the static one conserve their mass to roundoff, keep the maximum
+    principle of beta = 1/2 (no mass leaves [0, max m0]), keep every particle
+    in the box, and the walking sim keeps the pair count of its uniform
+    density; the step counters add up."""
+    for w, steps in ((W.rw2d(n=400_000, precision=W.FP32W_FP64ACC), 4000),
+                     (W.plain2d(n=10_000, precision=W.FP64), 5000)):
+        m, x, st = gpu_run(mt, w, steps)
+        assert st["nonfinite"] == 0 and st["steps_done"] == steps
+        assert st["drift"] < 1e-11, st["drift"]
+        assert m.min() >= -1e-15 and m.max() <= w.m0.max() * (1 + 1e-12)
+        assert np.all((x >= 0) & (x <= w.params.hi[0]))
+        per = st["pairs_last"] / w.params.n
+        say(f"  {w.name} {steps} steps: drift {st['drift']:.3e}, pairs/particle {per:.3f}, "
+            f"pairs total {st['pairs_total']}")
+        if w.params.d_rw > 0:
+            # pi psi^2 at density 1 (5.65), less the walls' share
+            assert 5.4 < per < 5.70, per
+        assert st["pairs_total"] >= st["pairs_last"] * steps * 0.98
